@@ -1,0 +1,137 @@
+/*
+ * gf2pls -- PLS decomposition and reduced row echelon form of dense GF(2)
+ * matrices on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Albrecht & Pernet, "Efficient Decomposition of Dense Matrices over
+ * GF(2)".  The decomposition follows the problem statement of Section 2
+ * (Proposition "PLS decomposition": any m x n matrix A of rank r can be written
+ * A = P L S, P an m x m permutation, L m x r unit lower triangular, S r x n upper
+ * triangular up to a column permutation, here chosen in row echelon form), computed
+ * in place as in Sections 4-5 (L below the main diagonal, S on and above it).
+ *
+ * Conventions shared by every call
+ *  - Matrices are bit-packed row-major in 64-bit words: column j of row i is bit
+ *    (j mod 64) of words[i * stride + j / 64].  Bits past column n must be zero
+ *    on input and stay zero.  `words` is a DEVICE pointer, 8-byte aligned.
+ *  - Permutations use the transposition ("swap sequence") form of the paper's
+ *    algorithms: step i exchanged rows i and P[i] (i < r, P[i] >= i); pivot i lies
+ *    in column Q[i].  P[i] = i for i >= r and Q[i] = i for r <= i < n.  Indices
+ *    are 0-based int32 in DEVICE memory.
+ *  - The caller owns every buffer.  No call allocates device memory; scratch
+ *    space comes from a caller-provided workspace of the size the matching
+ *    *_workspace_bytes call reports.  The library keeps no pointer after a call.
+ *  - Calls are asynchronous on the given stream (a hipStream_t passed as void*;
+ *    NULL is the default stream).  Arguments are validated on the host before
+ *    anything is enqueued, so on error nothing is written.
+ *  - Return value: GF2_OK (0) or a negative gf2_status.
+ *  - A gf2_ctx is not thread-safe; use one per host thread.
+ */
+#ifndef GF2PLS_H
+#define GF2PLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gf2_status {
+    GF2_OK = 0,
+    GF2_E_ARG = -1,         /* bad size, null pointer or out-of-range schedule     */
+    GF2_E_ALIGN = -2,       /* stride < ceil(n/64) or misaligned pointer          */
+    GF2_E_WORKSPACE = -3,   /* workspace missing or smaller than required         */
+    GF2_E_HIP = -4,         /* a HIP runtime call failed                          */
+    GF2_E_UNSUPPORTED = -5  /* size outside the supported range                   */
+} gf2_status;
+
+typedef struct gf2_ctx gf2_ctx;
+
+/* A dense packed GF(2) matrix (device memory). */
+typedef struct gf2_mat {
+    uint64_t *words;
+    int64_t m, n;
+    int64_t stride; /* words per row, >= ceil(n / 64) */
+} gf2_mat;
+
+/* Schur-update variants for the recursive PLS (Section 5: A_SE <- A_SE + A_SW A_NE). */
+enum { GF2_SCHUR_XOR = 0,   /* AND / XOR-popcount on the vector ALUs              */
+       GF2_SCHUR_MFMA = 1   /* int8 MFMA, int32 accumulation, reduced mod 2       */ };
+
+/*
+ * Schedule.  Changes timing only, never a result bit.
+ *  k       Gray-table width in bits for the table-driven updates (MakeTable1 /
+ *          AddRowsFromTable, Section 4.1), 4..8.
+ *  tables  tables applied per pass over the rows, 1, 2, 4 or 8.
+ *  cutoff  recursion cutoff in columns (Section 6): column blocks of at most
+ *          `cutoff` columns are factored by the MMPF base case.  Multiple of 64,
+ *          64..2^30.  cutoff >= n runs MMPF alone.
+ *  schur   GF2_SCHUR_XOR or GF2_SCHUR_MFMA.
+ */
+typedef struct gf2_sched {
+    int32_t k;
+    int32_t tables;
+    int32_t cutoff;
+    int32_t schur;
+} gf2_sched;
+
+/* Create a context on HIP device `device` (0-based).  *out is set on success. */
+int gf2_ctx_create(gf2_ctx **out, int device);
+void gf2_ctx_destroy(gf2_ctx *ctx);
+
+/* Human-readable name of a status code (static storage). */
+const char *gf2_status_str(int status);
+
+/* The fixed default schedule, the fallback of any tuned or learned choice. */
+void gf2_default_sched(gf2_sched *out);
+
+/* Non-zero if `s` is a valid schedule. */
+int gf2_sched_valid(const gf2_sched *s);
+
+/* Workspace bytes gf2_pls needs for an m x n matrix under schedule s (NULL: default). */
+size_t gf2_pls_workspace_bytes(int64_t m, int64_t n, const gf2_sched *s);
+
+/*
+ * PLS decomposition in place (Sections 4-5).
+ * A is overwritten with the compressed in-place form: for i < r, columns < i of
+ * row i hold L[i][.], column i holds 1, columns (i, Q[i]] hold 0 and columns
+ * > Q[i] hold S[i][.]; for i >= r, columns < r hold L[i][.] and the rest 0.
+ * P (m entries), Q (n entries) and *rank (one int32) are device pointers.
+ * The result is identical to Gaussian PLS (Appendix A) for every schedule.
+ * s == NULL selects the default schedule.
+ */
+int gf2_pls(gf2_ctx *ctx, gf2_mat A, int32_t *P, int32_t *Q, int32_t *rank,
+            const gf2_sched *s, void *ws, size_t ws_bytes, void *stream);
+
+/* Workspace bytes gf2_rref needs. */
+size_t gf2_rref_workspace_bytes(int64_t m, int64_t n);
+
+/*
+ * Reduced row echelon form from a PLS (timed with the decomposition in the
+ * paper's Table 1; Definition "Reduced Row Echelon Form", Section 2).
+ * A_pls, Q and rank are gf2_pls outputs (device); A_pls is only read.
+ * R_out (m x n, same shape as A_pls, its own buffer) receives the RREF of the
+ * original A: rows < r in reduced echelon form with leading ones at Q[0..r),
+ * rows >= r zero.
+ */
+int gf2_rref(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int32_t *rank,
+             gf2_mat R_out, void *ws, size_t ws_bytes, void *stream);
+
+/* Workspace bytes gf2_addmul needs for C (m x n) += A (m x k) * B (k x n). */
+size_t gf2_addmul_workspace_bytes(int64_t m, int64_t k, int64_t n);
+
+/*
+ * GF(2) matrix product accumulate C <- C + A * B, the Schur-complement update
+ * of Section 5 (A_SE <- A_SE + A_SW * A_NE), exposed for direct use and tests.
+ * A is m x k, B is k x n, C is m x n, all device matrices with their own
+ * strides; C must not overlap A or B.  `variant` is GF2_SCHUR_XOR or
+ * GF2_SCHUR_MFMA; both give identical bits.
+ */
+int gf2_addmul(gf2_ctx *ctx, gf2_mat C, gf2_mat A, gf2_mat B, int variant,
+               void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GF2PLS_H */

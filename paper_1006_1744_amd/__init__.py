@@ -1,0 +1,198 @@
+"""gf2pls: PLS decomposition and RREF of dense GF(2) matrices on MI355X (gfx950).
+
+Thin ctypes binding over ``libgf2pls.so`` (see ``include/gf2pls.h``).  Every
+step of the method runs in the library's HIP kernels; PyTorch only provides
+device memory and the stream.  There is no CPU fallback: if the library is
+missing, importing the binding raises.
+
+Matrices are ``torch.int64`` CUDA tensors of shape ``(m, stride)`` holding the
+bit-packed rows (column j of row i is bit j % 64 of word j // 64, LSB first).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+from .build import LIB as _LIB_PATH
+
+__all__ = ["Sched", "Mat", "get_lib", "default_sched", "pls", "rref", "addmul", "to_device",
+           "to_host", "workspace", "SCHUR_XOR", "SCHUR_MFMA", "GF2Error"]
+
+SCHUR_XOR = 0
+SCHUR_MFMA = 1
+
+
+class GF2Error(RuntimeError):
+    pass
+
+
+class Mat(ctypes.Structure):
+    _fields_ = [("words", ctypes.c_void_p), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("stride", ctypes.c_int64)]
+
+
+class Sched(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("tables", ctypes.c_int32), ("cutoff", ctypes.c_int32),
+                ("schur", ctypes.c_int32)]
+
+    def astuple(self):
+        return (self.k, self.tables, self.cutoff, self.schur)
+
+    def __repr__(self):
+        return f"Sched(k={self.k}, tables={self.tables}, cutoff={self.cutoff}, schur={self.schur})"
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is not built; run python -m paper_1006_1744_amd.build")
+    L = ctypes.CDLL(_LIB_PATH)
+    vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
+    L.gf2_ctx_create.argtypes = [ctypes.POINTER(vp), i32]
+    L.gf2_ctx_create.restype = i32
+    L.gf2_ctx_destroy.argtypes = [vp]
+    L.gf2_ctx_destroy.restype = None
+    L.gf2_status_str.argtypes = [i32]
+    L.gf2_status_str.restype = ctypes.c_char_p
+    L.gf2_default_sched.argtypes = [ctypes.POINTER(Sched)]
+    L.gf2_default_sched.restype = None
+    L.gf2_sched_valid.argtypes = [ctypes.POINTER(Sched)]
+    L.gf2_sched_valid.restype = i32
+    L.gf2_pls_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(Sched)]
+    L.gf2_pls_workspace_bytes.restype = sz
+    L.gf2_pls.argtypes = [vp, Mat, vp, vp, vp, ctypes.POINTER(Sched), vp, sz, vp]
+    L.gf2_pls.restype = i32
+    L.gf2_rref_workspace_bytes.argtypes = [i64, i64]
+    L.gf2_rref_workspace_bytes.restype = sz
+    L.gf2_rref.argtypes = [vp, Mat, vp, vp, Mat, vp, sz, vp]
+    L.gf2_rref.restype = i32
+    L.gf2_addmul_workspace_bytes.argtypes = [i64, i64, i64]
+    L.gf2_addmul_workspace_bytes.restype = sz
+    L.gf2_addmul.argtypes = [vp, Mat, Mat, Mat, i32, vp, sz, vp]
+    L.gf2_addmul.restype = i32
+    return L
+
+
+_lib_handle = None
+_ctx = {}
+
+
+def get_lib():
+    """The loaded libgf2pls (raises ImportError if it has not been built)."""
+    global _lib_handle
+    if _lib_handle is None:
+        _lib_handle = _load()
+    return _lib_handle
+
+
+def __getattr__(name):
+    if name == "lib":
+        return get_lib()
+    raise AttributeError(name)
+
+
+def ctx(device: int | None = None):
+    dev = torch.cuda.current_device() if device is None else device
+    if dev not in _ctx:
+        h = ctypes.c_void_p()
+        _check(get_lib().gf2_ctx_create(ctypes.byref(h), dev))
+        _ctx[dev] = h
+    return _ctx[dev]
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise GF2Error(f"gf2 error {rc}: {get_lib().gf2_status_str(rc).decode()}")
+
+
+def default_sched() -> Sched:
+    s = Sched()
+    get_lib().gf2_default_sched(ctypes.byref(s))
+    return s
+
+
+def sched(k=8, tables=8, cutoff=512, schur=SCHUR_MFMA) -> Sched:
+    return Sched(k, tables, cutoff, schur)
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _mat(t: torch.Tensor, m: int, n: int) -> Mat:
+    if t.dtype != torch.int64 or not t.is_cuda or t.dim() != 2 or not t.is_contiguous():
+        raise ValueError("matrix must be a contiguous 2-D int64 CUDA tensor")
+    if t.shape[0] != m:
+        raise ValueError("row count mismatch")
+    return Mat(t.data_ptr(), m, n, t.shape[1])
+
+
+def workspace(nbytes: int, device=None) -> torch.Tensor:
+    """Caller-owned workspace (256-byte aligned by the caching allocator)."""
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8,
+                       device=device if device is not None else "cuda")
+
+
+def to_device(a, device="cuda") -> torch.Tensor:
+    """numpy uint64 (m, stride) -> int64 CUDA tensor with the same bits."""
+    import numpy as np
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to(device)
+
+
+def to_host(t: torch.Tensor):
+    import numpy as np
+    return t.cpu().numpy().view(np.uint64)
+
+
+def pls_workspace_bytes(m: int, n: int, s: Sched | None = None) -> int:
+    return int(get_lib().gf2_pls_workspace_bytes(m, n, ctypes.byref(s) if s is not None else None))
+
+
+def pls(A: torch.Tensor, m: int, n: int, s: Sched | None = None, ws: torch.Tensor | None = None,
+        P: torch.Tensor | None = None, Q: torch.Tensor | None = None,
+        rank: torch.Tensor | None = None, stream=None):
+    """In-place PLS of A.  Returns (P, Q, rank) int32 CUDA tensors (asynchronous)."""
+    dev = A.device
+    nb = pls_workspace_bytes(m, n, s)
+    if nb == 0:
+        raise GF2Error("invalid size or schedule")
+    if ws is None or ws.numel() < nb:
+        ws = workspace(nb, dev)
+    P = torch.empty(max(m, 1), dtype=torch.int32, device=dev) if P is None else P
+    Q = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if Q is None else Q
+    rank = torch.empty(1, dtype=torch.int32, device=dev) if rank is None else rank
+    _check(get_lib().gf2_pls(ctx(dev.index), _mat(A, m, n), P.data_ptr(), Q.data_ptr(), rank.data_ptr(),
+                       ctypes.byref(s) if s is not None else None, ws.data_ptr(), ws.numel(),
+                       _stream(stream)))
+    return P[:m], Q[:n], rank
+
+
+def rref_workspace_bytes(m: int, n: int) -> int:
+    return int(get_lib().gf2_rref_workspace_bytes(m, n))
+
+
+def rref(A_pls: torch.Tensor, m: int, n: int, Q: torch.Tensor, rank: torch.Tensor,
+         R: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None):
+    """RREF of the original matrix from its PLS; returns R (m, stride) int64."""
+    dev = A_pls.device
+    R = torch.empty_like(A_pls) if R is None else R
+    nb = rref_workspace_bytes(m, n)
+    if ws is None or ws.numel() < nb:
+        ws = workspace(nb, dev)
+    _check(get_lib().gf2_rref(ctx(dev.index), _mat(A_pls, m, n), Q.data_ptr(), rank.data_ptr(),
+                        _mat(R, m, n), ws.data_ptr(), ws.numel(), _stream(stream)))
+    return R
+
+
+def addmul(C: torch.Tensor, A: torch.Tensor, B: torch.Tensor, m: int, k: int, n: int,
+           variant: int = SCHUR_MFMA, ws: torch.Tensor | None = None, stream=None):
+    """C <- C + A * B over GF(2) (A m x k, B k x n, C m x n)."""
+    dev = C.device
+    nb = int(get_lib().gf2_addmul_workspace_bytes(m, k, n))
+    if ws is None or ws.numel() < nb:
+        ws = workspace(nb, dev)
+    _check(get_lib().gf2_addmul(ctx(dev.index), _mat(C, m, n), _mat(A, m, k), _mat(B, k, n), variant,
+                          ws.data_ptr(), ws.numel(), _stream(stream)))
+    return C

@@ -1,0 +1,463 @@
+// C-ABI entry points of libgf2pls and the host-side driver of the recursion.
+//
+// gf2_pls follows the asymptotically fast PLS of Section 5: columns are split at
+// word boundaries (Section 6: cuts along word boundaries), the left half is
+// decomposed, the right half receives the row swaps (done eagerly inside the
+// panel kernels), the triangular solve A_NE <- L_NW^{-1} A_NE and the Schur
+// update A_SE <- A_SE + A_SW A_NE, then the right half is decomposed and the L
+// columns are compressed.  Column blocks of at most `cutoff` columns use the
+// MMPF base case of Section 4.1, with 64-column panels (PlsSubmatrix re-planned
+// for one wave) followed by table-driven updates (MakeTable1 /
+// AddRowsFromTable).  All launches go to one stream; data-dependent extents
+// are read on the device, so the host never waits.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "../../include/gf2pls.h"
+#include "gf2_internal.h"
+
+struct gf2_ctx {
+    int device;
+    int cus;
+};
+
+namespace gf2 {
+int table_update_tile_words(int k, int tables);
+}
+
+using namespace gf2;
+
+namespace {
+
+constexpr int64_t kMaxDim = (int64_t)1 << 30;
+constexpr int kMfmaMaxK = 65536;   // int32 sums of +-128*128 products stay exact
+constexpr int kINF = 0x3fffffff;
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool sched_ok(const gf2_sched *s) {
+    if (!s) return false;
+    if (s->k < 4 || s->k > 8) return false;
+    if (s->tables != 1 && s->tables != 2 && s->tables != 4 && s->tables != 8) return false;
+    if (s->cutoff < 64 || (s->cutoff % 64) != 0) return false;
+    if (s->schur != GF2_SCHUR_XOR && s->schur != GF2_SCHUR_MFMA) return false;
+    return true;
+}
+
+gf2_sched default_sched() {
+    gf2_sched s;
+    s.k = 8;
+    s.tables = 8;
+    s.cutoff = 512;
+    s.schur = GF2_SCHUR_MFMA;
+    return s;
+}
+
+// C rows `crows` (of C, default end m), words [cw, cw + nw) += A (same rows, K
+// bits from word aw) * B (rows `brows` of Bsrc, default end kmrows, words
+// [cw, cw + nw) of Bsrc), K <= kmax, split into chunks the MFMA sums keep exact.
+hipError_t enqueue_gemm(uint64_t *C, int64_t sc, const uint64_t *Am, int64_t sa,
+                        const uint64_t *Bsrc, int64_t sb, int m, int kmrows, RowRange crows,
+                        int aw, int cw, int nw, RowRange brows, int kmax, int schur,
+                        const int32_t *rk, uint64_t *Bt, hipStream_t st) {
+    for (int k0 = 0; k0 < kmax; k0 += kMfmaMaxK) {
+        const int kc = std::min(kMfmaMaxK, kmax - k0);
+        RowRange br = brows;
+        br.a += k0;
+        br.s = std::min(br.s - k0, kc);
+        const int64_t sbt = (kc + 63) / 64;
+        hipError_t e = launch_transpose(Bsrc, sb, kmrows, br, cw, nw, kc, Bt, sbt, rk, st);
+        if (e != hipSuccess) return e;
+        if (schur == GF2_SCHUR_MFMA)
+            e = launch_gemm_mfma(C, sc, Am, sa, m, crows, aw + k0 / 64, cw, nw, Bt, sbt, kc, br,
+                                 kmrows, rk, st);
+        else
+            e = launch_gemm_xor(C, sc, Am, sa, m, crows, aw + k0 / 64, cw, nw, Bt, sbt, kc, br,
+                                kmrows, rk, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+size_t gemm_bt_words(int nw, int kmax) {
+    const int kc = std::min(kMfmaMaxK, kmax);
+    return (size_t)nw * 64 * ((kc + 63) / 64);
+}
+
+#define GF2_TRY(x)                                   \
+    do {                                             \
+        hipError_t e_ = (x);                         \
+        if (e_ != hipSuccess) return GF2_E_HIP;      \
+    } while (0)
+
+// The recursion, run either to size the workspace (dry) or to launch.
+struct PlsDriver {
+    bool dry = true;
+    uint64_t *A = nullptr;
+    int64_t stride = 0;
+    int m = 0, n = 0, nb = 0;
+    gf2_sched s{};
+    int32_t *rk = nullptr, *P = nullptr, *Q = nullptr, *info = nullptr;
+    uint64_t *Bt = nullptr;
+    size_t bt_words = 0;   // capacity (launch) or requirement (dry)
+    hipStream_t st = nullptr;
+    hipError_t err = hipSuccess;
+
+    void chk(hipError_t e) {
+        if (err == hipSuccess && e != hipSuccess) err = e;
+    }
+
+    // C rows `crows`, C words [cw, cw + nw) += A (rows = crows, K bits from word aw)
+    // times B (rows `brows`, same words as C), K <= kmax.
+    void gemm(RowRange crows, int aw, int cw, int nw, RowRange brows, int kmax) {
+        if (nw <= 0 || kmax <= 0) return;
+        if (dry) {
+            bt_words = std::max(bt_words, gemm_bt_words(nw, kmax));
+            return;
+        }
+        chk(enqueue_gemm(A, stride, A, stride, A, stride, m, m, crows, aw, cw, nw, brows, kmax,
+                         s.schur, rk, Bt, st));
+    }
+
+    // rows [rk[ib] + a, min(rk[ie], rk[ib] + a + sz)) <- L^{-1} rows, L's block
+    // starting at word lw0 + a / 64; right-hand side words [w_lo, w_hi).
+    void trsm_lower(int ib, int ie, int a, int sz, int lw0, int w_lo, int w_hi) {
+        if (w_hi <= w_lo || sz <= 0) return;
+        if (sz <= 64) {
+            if (!dry)
+                chk(launch_trsm_base(A, stride, A, stride, m, row_range(ib, ie, a, sz),
+                                     lw0 + a / 64, w_lo, w_hi, rk, 1, st));
+            return;
+        }
+        const int h = (sz / 64 / 2) * 64;
+        trsm_lower(ib, ie, a, h, lw0, w_lo, w_hi);
+        gemm(row_range(ib, ie, a + h, sz - h), lw0 + a / 64, w_lo, w_hi - w_lo,
+             row_range(ib, ie, a, h), h);
+        trsm_lower(ib, ie, a + h, sz - h, lw0, w_lo, w_hi);
+    }
+
+    // MMPF base case on word columns [wb, wb + nwd): 64-column panels, each
+    // followed by the triangular solve of its pivot rows and the table update of
+    // the rows below, on the block's remaining columns.
+    void base(int wb, int nwd) {
+        for (int p = 0; p < nwd; p++) {
+            const int wc = wb + p;
+            if (!dry) chk(launch_leaf(A, stride, m, n, wc, rk, wc, P, Q, info, st));
+            if (p + 1 < nwd && !dry) {
+                chk(launch_trsm_base(A, stride, A, stride, m, row_range(wc, wc + 1, 0, 64), wc,
+                                     wc + 1, wb + nwd, rk, 1, st));
+                chk(launch_table_update(A, stride, m, wc, rk, wc, wc + 1, wb + nwd, s.k, s.tables,
+                                        st));
+            }
+        }
+        for (int p = nwd - 2; p >= 0; p--)
+            if (!dry)
+                chk(launch_compress_shift(A, stride, m, 64 * (wb + p), 64, rk, wb + p, wb + p + 1,
+                                          wb + nwd, st));
+    }
+
+    void node(int wb, int nwd) {
+        if (nwd <= 0) return;
+        if (nwd == 1 || (int64_t)nwd * 64 <= s.cutoff) {
+            base(wb, nwd);
+            return;
+        }
+        const int h = nwd / 2;
+        node(wb, h);
+        // A_NE <- L_NW^{-1} A_NE on the first half's pivot rows
+        trsm_lower(wb, wb + h, 0, 64 * h, wb, wb + h, wb + nwd);
+        // A_SE <- A_SE + A_SW A_NE
+        gemm(row_range(wb + h, -1, 0, kINF), wb, wb + h, nwd - h, row_range(wb, wb + h, 0, 64 * h),
+             64 * h);
+        node(wb + h, nwd - h);
+        if (!dry)
+            chk(launch_compress_shift(A, stride, m, 64 * wb, 64 * h, rk, wb, wb + h, wb + nwd, st));
+    }
+
+    void run() {
+        if (!dry) chk(launch_fill_i32(rk, 0, nb + 1, st));
+        node(0, nb);
+    }
+};
+
+struct PlsLayout {
+    size_t rk_off, info_off, bt_off, total;
+    size_t bt_words;
+};
+
+PlsLayout pls_layout(int64_t m, int64_t n, const gf2_sched &s) {
+    PlsDriver d;
+    d.dry = true;
+    d.m = (int)m;
+    d.n = (int)n;
+    d.nb = (int)((n + 63) / 64);
+    d.s = s;
+    d.run();
+    PlsLayout L;
+    size_t off = 0;
+    L.rk_off = off;
+    off = align_up(off + (size_t)(d.nb + 2) * 4);
+    L.info_off = off;
+    off = align_up(off + panel_info_bytes());
+    L.bt_off = off;
+    L.bt_words = d.bt_words;
+    off = align_up(off + d.bt_words * 8);
+    L.total = off;
+    return L;
+}
+
+int check_mat(const gf2_mat &A) {
+    if (A.m < 0 || A.n < 0 || A.m > kMaxDim || A.n > kMaxDim) return GF2_E_UNSUPPORTED;
+    if (A.stride < (A.n + 63) / 64) return GF2_E_ALIGN;
+    if ((A.m > 0 && A.n > 0) && !A.words) return GF2_E_ARG;
+    if (((uintptr_t)A.words & 7) != 0) return GF2_E_ALIGN;
+    if (A.stride > ((int64_t)1 << 40) / std::max<int64_t>(A.m, 1)) return GF2_E_UNSUPPORTED;
+    return GF2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gf2_ctx_create(gf2_ctx **out, int device) {
+    if (!out) return GF2_E_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess) return GF2_E_HIP;
+    if (device < 0 || device >= count) return GF2_E_ARG;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return GF2_E_HIP;
+    gf2_ctx *c = new gf2_ctx;
+    c->device = device;
+    c->cus = prop.multiProcessorCount;
+    *out = c;
+    return GF2_OK;
+}
+
+void gf2_ctx_destroy(gf2_ctx *ctx) { delete ctx; }
+
+const char *gf2_status_str(int status) {
+    switch (status) {
+        case GF2_OK: return "ok";
+        case GF2_E_ARG: return "invalid argument";
+        case GF2_E_ALIGN: return "stride or alignment";
+        case GF2_E_WORKSPACE: return "workspace too small";
+        case GF2_E_HIP: return "HIP runtime error";
+        case GF2_E_UNSUPPORTED: return "unsupported size";
+        default: return "unknown status";
+    }
+}
+
+void gf2_default_sched(gf2_sched *out) {
+    if (out) *out = default_sched();
+}
+
+int gf2_sched_valid(const gf2_sched *s) { return sched_ok(s) ? 1 : 0; }
+
+size_t gf2_pls_workspace_bytes(int64_t m, int64_t n, const gf2_sched *s) {
+    if (m < 0 || n < 0 || m > kMaxDim || n > kMaxDim) return 0;
+    gf2_sched ss = s ? *s : default_sched();
+    if (!sched_ok(&ss)) return 0;
+    return pls_layout(m, n, ss).total;
+}
+
+int gf2_pls(gf2_ctx *ctx, gf2_mat A, int32_t *P, int32_t *Q, int32_t *rank, const gf2_sched *s,
+            void *ws, size_t ws_bytes, void *stream) {
+    if (!ctx) return GF2_E_ARG;
+    int rc = check_mat(A);
+    if (rc != GF2_OK) return rc;
+    gf2_sched ss = s ? *s : default_sched();
+    if (!sched_ok(&ss)) return GF2_E_ARG;
+    if (!rank || (A.m > 0 && !P) || (A.n > 0 && !Q)) return GF2_E_ARG;
+    PlsLayout L = pls_layout(A.m, A.n, ss);
+    if (!ws || ws_bytes < L.total) return GF2_E_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return GF2_E_ALIGN;
+    hipStream_t st = (hipStream_t)stream;
+    if (hipSetDevice(ctx->device) != hipSuccess) return GF2_E_HIP;
+    char *base = (char *)ws;
+    PlsDriver d;
+    d.dry = false;
+    d.A = A.words;
+    d.stride = A.stride;
+    d.m = (int)A.m;
+    d.n = (int)A.n;
+    d.nb = (int)((A.n + 63) / 64);
+    d.s = ss;
+    d.rk = (int32_t *)(base + L.rk_off);
+    d.info = (int32_t *)(base + L.info_off);
+    d.Bt = (uint64_t *)(base + L.bt_off);
+    d.bt_words = L.bt_words;
+    d.P = P;
+    d.Q = Q;
+    d.st = st;
+    if (A.m > 0 && A.n > 0) d.run();
+    else d.chk(launch_fill_i32(d.rk, 0, d.nb + 1, st));
+    d.chk(launch_finalize(P, Q, rank, d.rk, d.nb, d.m, d.n, st));
+    return d.err == hipSuccess ? GF2_OK : GF2_E_HIP;
+}
+
+}  // extern "C"
+
+namespace {
+struct RrefLayout {
+    size_t rr, pm, nm, pp, pn, uc, xc, bt, total;
+    int64_t su, sx;
+    int rmax;
+};
+
+RrefLayout rref_layout(int64_t m, int64_t n) {
+    RrefLayout L;
+    const int64_t nw = std::max<int64_t>((n + 63) / 64, 1);
+    L.rmax = (int)std::min(m, n);
+    L.su = std::max<int64_t>((L.rmax + 63) / 64, 1);
+    L.sx = nw;
+    size_t off = 0;
+    L.rr = off; off = align_up(off + 16);
+    L.pm = off; off = align_up(off + nw * 8);
+    L.nm = off; off = align_up(off + nw * 8);
+    L.pp = off; off = align_up(off + (nw + 1) * 4);
+    L.pn = off; off = align_up(off + (nw + 1) * 4);
+    L.uc = off; off = align_up(off + (size_t)std::max(L.rmax, 1) * L.su * 8);
+    L.xc = off; off = align_up(off + (size_t)std::max(L.rmax, 1) * L.sx * 8);
+    L.bt = off;
+    off = align_up(off + gemm_bt_words((int)nw, std::max(64, (L.rmax / 64 / 2 + 1) * 64)) * 8);
+    L.total = off;
+    return L;
+}
+
+struct UpperSolve {
+    uint64_t *X;
+    int64_t sx;
+    const uint64_t *U;
+    int64_t su;
+    int r, nwx;
+    const int32_t *rr;
+    uint64_t *Bt;
+    hipStream_t st;
+    hipError_t err = hipSuccess;
+    void chk(hipError_t e) {
+        if (err == hipSuccess && e != hipSuccess) err = e;
+    }
+    // rows [a, min(r, a + sz)) <- U^{-1} rows, solving the last rows first
+    void solve(int a, int sz) {
+        if (a >= r || sz <= 0) return;
+        if (sz <= 64) {
+            chk(launch_trsm_base(X, sx, U, su, r, row_range(-1, -1, a, sz), a / 64, 0, nwx, rr, 0,
+                                 st));
+            return;
+        }
+        const int h = (sz / 64 / 2) * 64;
+        solve(a + h, sz - h);
+        if (a + h < r)
+            chk(enqueue_gemm(X, sx, U, su, X, sx, r, r, row_range(-1, -1, a, h), (a + h) / 64, 0,
+                             nwx, row_range(-1, -1, a + h, sz - h), sz - h, GF2_SCHUR_MFMA, rr,
+                             Bt, st));
+        solve(a, h);
+    }
+};
+}  // namespace
+
+extern "C" size_t gf2_rref_workspace_bytes(int64_t m, int64_t n) {
+    if (m < 0 || n < 0 || m > kMaxDim || n > kMaxDim) return 0;
+    return rref_layout(m, n).total;
+}
+
+extern "C" int gf2_rref(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int32_t *rank,
+                        gf2_mat R_out, void *ws, size_t ws_bytes, void *stream) {
+    if (!ctx) return GF2_E_ARG;
+    int rc;
+    if ((rc = check_mat(A_pls)) != GF2_OK) return rc;
+    if ((rc = check_mat(R_out)) != GF2_OK) return rc;
+    if (R_out.m != A_pls.m || R_out.n != A_pls.n) return GF2_E_ARG;
+    if (!rank || (A_pls.n > 0 && !Q)) return GF2_E_ARG;
+    if (R_out.words == A_pls.words && A_pls.m > 0) return GF2_E_ARG;
+    RrefLayout L = rref_layout(A_pls.m, A_pls.n);
+    if (!ws || ws_bytes < L.total) return GF2_E_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return GF2_E_ALIGN;
+    if (A_pls.m == 0 || A_pls.n == 0) return GF2_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return GF2_E_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    char *base = (char *)ws;
+    const int m = (int)A_pls.m, n = (int)A_pls.n;
+    uint64_t *PM = (uint64_t *)(base + L.pm), *NM = (uint64_t *)(base + L.nm);
+    int32_t *pp = (int32_t *)(base + L.pp), *pn = (int32_t *)(base + L.pn);
+    uint64_t *Uc = (uint64_t *)(base + L.uc), *Xc = (uint64_t *)(base + L.xc);
+    GF2_TRY(launch_rref_masks(PM, NM, pp, pn, Q, rank, n, L.rmax, st));
+    // the rank fixes every extent below: read it once
+    int32_t r = 0;
+    GF2_TRY(hipMemcpyAsync(&r, rank, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GF2_TRY(hipStreamSynchronize(st));
+    if (r < 0 || r > L.rmax) return GF2_E_ARG;
+    const int nwx = (n - r + 63) / 64;
+    if (r > 0) {
+        GF2_TRY(launch_zero_rows(Uc, L.su, r, (r + 63) / 64, st));
+        if (nwx > 0) GF2_TRY(launch_zero_rows(Xc, L.sx, r, nwx, st));
+        GF2_TRY(launch_rref_gather(A_pls.words, A_pls.stride, Q, r, n, PM, NM, pp, pn, Uc, L.su,
+                                   Xc, L.sx, st));
+        if (nwx > 0) {
+            UpperSolve us;
+            us.X = Xc; us.sx = L.sx; us.U = Uc; us.su = L.su; us.r = r; us.nwx = nwx;
+            us.rr = (const int32_t *)(base + L.rr); us.Bt = (uint64_t *)(base + L.bt); us.st = st;
+            us.solve(0, (r + 63) / 64 * 64);
+            if (us.err != hipSuccess) return GF2_E_HIP;
+        }
+    }
+    GF2_TRY(launch_rref_scatter(R_out.words, R_out.stride, m, n, Q, r, NM, pn, Xc, L.sx, st));
+    // zero the padding words of R past ceil(n/64)
+    const int nw = (n + 63) / 64;
+    if (R_out.stride > nw)
+        GF2_TRY(launch_zero_rows(R_out.words + nw, R_out.stride, m, (int)(R_out.stride - nw), st));
+    return GF2_OK;
+}
+
+extern "C" {
+
+size_t gf2_addmul_workspace_bytes(int64_t m, int64_t k, int64_t n) {
+    if (m < 0 || k < 0 || n < 0 || m > kMaxDim || k > kMaxDim || n > kMaxDim) return 0;
+    int64_t kc = std::min<int64_t>(k, kMfmaMaxK);
+    size_t bt = (size_t)((n + 63) / 64) * 64 * ((kc + 63) / 64);
+    return align_up(256) + align_up(bt * 8);
+}
+
+int gf2_addmul(gf2_ctx *ctx, gf2_mat C, gf2_mat A, gf2_mat B, int variant, void *ws,
+               size_t ws_bytes, void *stream) {
+    if (!ctx) return GF2_E_ARG;
+    int rc;
+    if ((rc = check_mat(C)) != GF2_OK) return rc;
+    if ((rc = check_mat(A)) != GF2_OK) return rc;
+    if ((rc = check_mat(B)) != GF2_OK) return rc;
+    if (A.m != C.m || B.n != C.n || A.n != B.m) return GF2_E_ARG;
+    if (variant != GF2_SCHUR_XOR && variant != GF2_SCHUR_MFMA) return GF2_E_ARG;
+    size_t need = gf2_addmul_workspace_bytes(C.m, A.n, C.n);
+    if (!ws || ws_bytes < need) return GF2_E_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return GF2_E_ALIGN;
+    if (C.m == 0 || C.n == 0 || A.n == 0) return GF2_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return GF2_E_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    int32_t *rk = (int32_t *)ws;
+    uint64_t *Bt = (uint64_t *)((char *)ws + align_up(256));
+    const int m = (int)C.m, K = (int)A.n, nw = (int)((C.n + 63) / 64);
+    // rk[0] = 0, rk[1] = K: rows of B are [rk[0], rk[1])
+    GF2_TRY(launch_fill_i32(rk, 0, 1, st));
+    GF2_TRY(launch_fill_i32(rk + 1, K, 1, st));
+    for (int k0 = 0; k0 < K; k0 += kMfmaMaxK) {
+        const int kc = std::min(kMfmaMaxK, K - k0);
+        RowRange br = row_range(0, 1, k0, kc);
+        const int64_t sbt = (kc + 63) / 64;
+        GF2_TRY(launch_transpose(B.words, B.stride, K, br, 0, nw, kc, Bt, sbt, rk, st));
+        RowRange cr = row_range(-1, -1, 0, kINF);
+        if (variant == GF2_SCHUR_MFMA)
+            GF2_TRY(launch_gemm_mfma(C.words, C.stride, A.words, A.stride, m, cr, k0 / 64, 0, nw, Bt,
+                                     sbt, kc, br, K, rk, st));
+        else
+            GF2_TRY(launch_gemm_xor(C.words, C.stride, A.words, A.stride, m, cr, k0 / 64, 0, nw, Bt,
+                                    sbt, kc, br, K, rk, st));
+    }
+    return GF2_OK;
+}
+
+}  // extern "C"

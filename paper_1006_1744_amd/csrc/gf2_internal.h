@@ -1,0 +1,117 @@
+// Internal declarations of the gfx950 kernels and their host-side launchers.
+//
+// Dynamic extents.  The recursion of Section 5 splits columns at fixed word
+// boundaries, so the sequence of kernel launches is known on the host; only the
+// ranks found so far are data-dependent.  They live in a device array `rk` with
+// one entry per 64-column panel: rk[b] is the rank of columns [0, 64*b).  Every
+// row range a kernel touches is an affine function of a few rk entries, given
+// as a RowRange and evaluated on the device, so no launch waits on the host.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gf2 {
+
+// Row range [start, end) with start = rk[ib] + a and
+// end = min(ie >= 0 ? rk[ie] : m, start + s)   (empty when end <= start).
+struct RowRange {
+    int32_t ib;
+    int32_t ie;
+    int32_t a;
+    int32_t s;
+};
+
+__host__ __device__ inline RowRange row_range(int ib, int ie, int a, int s) {
+    RowRange r;
+    r.ib = ib; r.ie = ie; r.a = a; r.s = s;
+    return r;
+}
+
+#ifdef __HIPCC__
+__device__ inline void eval_range(const int32_t *rk, int m, RowRange r, int &start, int &end) {
+    int base = r.ib >= 0 ? rk[r.ib] : 0;
+    start = base + r.a;
+    int hi = r.ie >= 0 ? rk[r.ie] : m;
+    long long lim = (long long)start + r.s;
+    end = (long long)hi < lim ? hi : (int)lim;
+    if (end < start) end = start;
+}
+#endif
+
+// Pairs of moved rows produced by a panel factorisation: count, then
+// (destination offset, source offset) pairs relative to the panel's first row.
+constexpr int kMaxMoved = 128;
+constexpr int kMovedInts = 1 + 2 * kMaxMoved;
+
+// ---------------------------------------------------------------- launchers
+// All return hipError_t of the launch.
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st);
+
+// Panel factorisation of the 64-column panel at word column wc, rows
+// [rk[b], m): pivots, row swaps inside the panel, L of every row, compressed.
+// Writes rk[b + 1], P and Q at the pivot slots, and the moved-row list.
+// Also moves the other words of the pivot rows (the full-row swaps).
+// `info` is a device scratch record of panel_info_bytes() bytes.
+hipError_t launch_leaf(uint64_t *A, int64_t stride, int m, int n, int wc, int32_t *rk, int b,
+                       int32_t *P, int32_t *Q, int32_t *info, hipStream_t st);
+size_t panel_info_bytes();
+
+// X <- L^{-1} X for at most 64 rows `rows` of X (matrix A) with the unit lower
+// triangular L taken from word column lw of the same rows of matrix Lm (bit i
+// of the block's row i is the diagonal), on word columns [w_lo, w_hi) of A.
+// lower = 0 solves with the unit upper triangle (bits > i) instead.
+hipError_t launch_trsm_base(uint64_t *A, int64_t stride, const uint64_t *Lm, int64_t sl, int m,
+                            RowRange rows, int lw, int w_lo, int w_hi, const int32_t *rk,
+                            int lower, hipStream_t st);
+
+// Table-driven update after a panel (Section 4.1: MakeTable1 / AddRowsFromTable):
+// rows [rk[b+1], m) on word columns [w_lo, w_hi) receive L * U, where L is the
+// row's panel word (compressed multipliers) and U the r = rk[b+1]-rk[b] pivot
+// rows on the same columns.  k bits per table, `tables` tables per pass.
+hipError_t launch_table_update(uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk,
+                               int b, int w_lo, int w_hi, int k, int tables, hipStream_t st);
+
+// Move the second block's L columns next to the first block's (Section 5,
+// final "compress L"): node at column c0 (multiple of 64), split n0 columns,
+// ranks r0 = rk[b1] - rk[b0], r1 = rk[b2] - rk[b1].
+hipError_t launch_compress_shift(uint64_t *A, int64_t stride, int m, int c0, int n0,
+                                 const int32_t *rk, int b0, int b1, int b2, hipStream_t st);
+
+// P[i] = i for i >= r, Q[i] = i for r <= i < n, *rank = r, with r = rk[nb].
+hipError_t launch_finalize(int32_t *P, int32_t *Q, int32_t *rank, const int32_t *rk, int nb,
+                           int m, int n, hipStream_t st);
+
+// Bit transpose: Bt (rows = 64 * nw bits of B's columns, words = ceil(kmax/64))
+// from B rows `brows` (K = their count), word columns [w_lo, w_lo + nw).
+// Rows of B beyond K read as zero.
+hipError_t launch_transpose(const uint64_t *B, int64_t sb, int m, RowRange brows, int w_lo,
+                            int nw, int kmax, uint64_t *Bt, int64_t sbt, const int32_t *rk,
+                            hipStream_t st);
+
+// C[rows, words w_lo..w_lo+nw) ^= A[rows, K bits from word aw] * B, with B given
+// transposed in Bt (64*nw rows of kmax bits, zero past K).  K is the length of
+// krows evaluated with kmrows as the default end.
+hipError_t launch_gemm_xor(uint64_t *C, int64_t sc, const uint64_t *A, int64_t sa, int m,
+                           RowRange rows, int aw, int w_lo, int nw, const uint64_t *Bt,
+                           int64_t sbt, int kmax, RowRange krows, int kmrows, const int32_t *rk,
+                           hipStream_t st);
+hipError_t launch_gemm_mfma(uint64_t *C, int64_t sc, const uint64_t *A, int64_t sa, int m,
+                            RowRange rows, int aw, int w_lo, int nw, const uint64_t *Bt,
+                            int64_t sbt, int kmax, RowRange krows, int kmrows, const int32_t *rk,
+                            hipStream_t st);
+
+// RREF helpers (k_rref.hip)
+hipError_t launch_zero_rows(uint64_t *X, int64_t sx, int rows, int words, hipStream_t st);
+hipError_t launch_rref_masks(uint64_t *PM, uint64_t *NM, int32_t *prefP, int32_t *prefN,
+                             const int32_t *Q, const int32_t *rank, int n, int rmax,
+                             hipStream_t st);
+hipError_t launch_rref_gather(const uint64_t *Ap, int64_t sap, const int32_t *Q, int r, int n,
+                              const uint64_t *PM, const uint64_t *NM, const int32_t *prefP,
+                              const int32_t *prefN, uint64_t *Uc, int64_t su, uint64_t *Xc,
+                              int64_t sx, hipStream_t st);
+hipError_t launch_rref_scatter(uint64_t *R, int64_t sr, int m, int n, const int32_t *Q, int r,
+                               const uint64_t *NM, const int32_t *prefN, const uint64_t *Xc,
+                               int64_t sx, hipStream_t st);
+
+}  // namespace gf2
