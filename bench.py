@@ -1,0 +1,135 @@
+"""Benchmark: PLS + RREF of a dense random 65536 x 65536 GF(2) matrix on one MI355X.
+
+One step = gf2_pls (recursive PLS, MMPF base case, Schur products on int8 MFMA)
+followed by gf2_rref on a fresh copy of the input already resident in HBM
+(every step has its own pristine copy, staged before the timed region).
+
+Prints ONE JSON line.  value = GF(2) operations per second, with the
+operation count 2*W, W = m n r - (m + n) r^2 / 2 + r^3 / 3 the classical
+multiply-add count of a rank-r PLS (2 n^3 / 3 for a full-rank square matrix).
+roofline: the dominant kernel (the int8-MFMA Schur product): its algorithmic
+operations 2*M*N*K per launch over its mean launch time, timed with HIP events
+on the launch stream during the timed steps, against the int8 dense MFMA peak.
+cpu_baseline: the CPU oracle (Gaussian PLS, Appendix A) timed on a smaller
+matrix of the same kind on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+INT8_MFMA_PEAK_TOPS = 5000.0   # MI355X dense int8 matrix-core peak (TOP/s)
+
+
+def classical_ops(m: int, n: int, r: int) -> float:
+    w = m * n * r - (m + n) * r * r / 2.0 + r ** 3 / 3.0
+    return 2.0 * w
+
+
+def cpu_baseline(n: int, seed: int) -> dict:
+    import oracle
+    import synth
+    A = synth.random_half(n, n, seed)
+    t0 = time.perf_counter()
+    r, P, Q, Ap = oracle.pls(A, n, n)
+    dt = time.perf_counter() - t0
+    return {"value": classical_ops(n, n, r) / dt, "unit": "GF(2) ops/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"Gaussian PLS (C, OpenMP) of one {n}x{n} Bernoulli(1/2) matrix, seed {seed}: "
+                      f"{dt:.2f} s, rank {r}"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--cpu-n", type=int, default=24576)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-rref", action="store_true")
+    ap.add_argument("--sched", type=str, default="")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus})", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1006_1744_amd as g
+    import synth
+
+    torch.cuda.set_device(0)
+    n = m = args.n
+    s = None
+    if args.sched:
+        k, t, c, sc = (int(x) for x in args.sched.split(","))
+        s = g.Sched(k, t, c, sc)
+    A = synth.random_half(m, n, args.seed)
+    host = g.to_device(A, "cpu")
+    del A
+    nsteps = args.steps + args.warmup
+    copies = [host.to("cuda") for _ in range(nsteps)]
+    del host
+    ws = g.workspace(max(g.pls_workspace_bytes(m, n, s), g.rref_workspace_bytes(m, n)))
+    P = torch.empty(m, dtype=torch.int32, device="cuda")
+    Q = torch.empty(n, dtype=torch.int32, device="cuda")
+    rank = torch.empty(1, dtype=torch.int32, device="cuda")
+    R = torch.empty_like(copies[0])
+
+    def step(i):
+        g.pls(copies[i], m, n, s, ws=ws, P=P, Q=Q, rank=rank)
+        if not args.no_rref:
+            g.rref(copies[i], m, n, Q, rank, R=R, ws=ws)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    g.prof_enable()
+    g.prof_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.warmup, nsteps):
+        step(i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = g.prof_read()
+    g.prof_disable()
+    r = int(rank.item())
+    ms = (t1 - t0) * 1e3 / args.steps
+    ops = classical_ops(m, n, r)
+    value = ops / (ms * 1e-3)
+
+    achieved = prof["ops"] / (prof["ms"] * 1e-3) / 1e12 if prof["ms"] > 0 else 0.0
+    roofline = {"bound": "mfma", "kernel": "gemm_mfma_kernel (int8 MFMA Schur product)",
+                "achieved": round(achieved, 1), "peak": INT8_MFMA_PEAK_TOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / INT8_MFMA_PEAK_TOPS, 4),
+                "traffic": None,
+                "launches_per_step": prof["launches"] // max(args.steps, 1),
+                "mean_launch_us": round(prof["ms"] * 1e3 / max(prof["launches"], 1), 2),
+                "kernel_share_of_step": round(prof["ms"] / args.steps / ms, 3)}
+    out = {"metric": "PLS+RREF of a dense random 65536x65536 GF(2) matrix (GF(2) ops/s)",
+           "value": value, "unit": "GF(2) ops/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u64/i8",
+           "data": "synthetic",
+           "config": {"workload": f"PLS + RREF, {m}x{n} iid Bernoulli(1/2), seed {args.seed}",
+                      "m": m, "n": n, "rank": r,
+                      "schedule": str(s) if s is not None else str(g.default_sched())},
+           "roofline": roofline}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.seed)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

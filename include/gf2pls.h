@@ -130,6 +130,25 @@ size_t gf2_addmul_workspace_bytes(int64_t m, int64_t k, int64_t n);
 int gf2_addmul(gf2_ctx *ctx, gf2_mat C, gf2_mat A, gf2_mat B, int variant,
                void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * Launch timing of the Schur-product kernels (diagnostics for roofline reports).
+ * gf2_prof_enable: dev_log is a caller-owned DEVICE array of 2 * log_slots int32
+ * (NULL disables).  While enabled, each product launch of gf2_pls / gf2_rref is
+ * bracketed by HIP events on its stream and writes its row count M and inner
+ * dimension K to the log (up to log_slots launches).
+ * gf2_prof_read: waits for the recorded events, returns the launch count, the
+ * summed event time and the summed algorithmic operations 2*M*N*K (one AND and
+ * one XOR per bit product), then clears the record.
+ */
+typedef struct gf2_prof_stats {
+    int64_t launches;
+    double total_ms;
+    double total_ops;
+} gf2_prof_stats;
+
+int gf2_prof_enable(gf2_ctx *ctx, int32_t *dev_log, int64_t log_slots);
+int gf2_prof_read(gf2_ctx *ctx, gf2_prof_stats *out);
+
 #ifdef __cplusplus
 }
 #endif

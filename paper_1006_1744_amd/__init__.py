@@ -44,6 +44,11 @@ class Sched(ctypes.Structure):
         return f"Sched(k={self.k}, tables={self.tables}, cutoff={self.cutoff}, schur={self.schur})"
 
 
+class ProfStats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("total_ops", ctypes.c_double)]
+
+
 def _load():
     if not os.path.exists(_LIB_PATH):
         raise ImportError(f"{_LIB_PATH} is not built; run python -m paper_1006_1744_amd.build")
@@ -71,6 +76,10 @@ def _load():
     L.gf2_addmul_workspace_bytes.restype = sz
     L.gf2_addmul.argtypes = [vp, Mat, Mat, Mat, i32, vp, sz, vp]
     L.gf2_addmul.restype = i32
+    L.gf2_prof_enable.argtypes = [vp, vp, i64]
+    L.gf2_prof_enable.restype = i32
+    L.gf2_prof_read.argtypes = [vp, ctypes.POINTER(ProfStats)]
+    L.gf2_prof_read.restype = i32
     return L
 
 
@@ -196,3 +205,29 @@ def addmul(C: torch.Tensor, A: torch.Tensor, B: torch.Tensor, m: int, k: int, n:
     _check(get_lib().gf2_addmul(ctx(dev.index), _mat(C, m, n), _mat(A, m, k), _mat(B, k, n), variant,
                           ws.data_ptr(), ws.numel(), _stream(stream)))
     return C
+
+
+_prof_logs = {}
+
+
+def prof_enable(slots: int = 1 << 16, device=None):
+    """Time every Schur-product launch with HIP events (see gf2_prof_enable)."""
+    dev = torch.cuda.current_device() if device is None else device
+    log = torch.zeros(2 * slots, dtype=torch.int32, device=f"cuda:{dev}")
+    _prof_logs[dev] = log
+    _check(get_lib().gf2_prof_enable(ctx(dev), log.data_ptr(), slots))
+
+
+def prof_disable(device=None):
+    dev = torch.cuda.current_device() if device is None else device
+    _check(get_lib().gf2_prof_enable(ctx(dev), None, 0))
+    _prof_logs.pop(dev, None)
+
+
+def prof_read(device=None) -> dict:
+    """Launch count, summed event milliseconds and summed 2*M*N*K of the product
+    launches recorded since the last read."""
+    dev = torch.cuda.current_device() if device is None else device
+    st = ProfStats()
+    _check(get_lib().gf2_prof_read(ctx(dev), ctypes.byref(st)))
+    return {"launches": int(st.launches), "ms": float(st.total_ms), "ops": float(st.total_ops)}

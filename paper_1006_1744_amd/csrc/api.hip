@@ -20,9 +20,22 @@
 #include "../../include/gf2pls.h"
 #include "gf2_internal.h"
 
+// Optional per-launch timing of the product kernels: events recorded on the
+// launch stream around each launch, the kernel storing its dynamic M and K in a
+// caller-provided device log.
+struct ProfRec {
+    hipEvent_t a, b;
+    int slot;
+    int ncols;
+};
+
 struct gf2_ctx {
     int device;
     int cus;
+    int32_t *plog = nullptr;
+    int64_t plog_cap = 0;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> pool;
 };
 
 namespace gf2 {
@@ -60,7 +73,16 @@ gf2_sched default_sched() {
 // C rows `crows` (of C, default end m), words [cw, cw + nw) += A (same rows, K
 // bits from word aw) * B (rows `brows` of Bsrc, default end kmrows, words
 // [cw, cw + nw) of Bsrc), K <= kmax, split into chunks the MFMA sums keep exact.
-hipError_t enqueue_gemm(uint64_t *C, int64_t sc, const uint64_t *Am, int64_t sa,
+hipEvent_t pool_event(gf2_ctx *ctx, size_t idx) {
+    while (ctx->pool.size() <= idx) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        ctx->pool.push_back(e);
+    }
+    return ctx->pool[idx];
+}
+
+hipError_t enqueue_gemm(gf2_ctx *ctx, uint64_t *C, int64_t sc, const uint64_t *Am, int64_t sa,
                         const uint64_t *Bsrc, int64_t sb, int m, int kmrows, RowRange crows,
                         int aw, int cw, int nw, RowRange brows, int kmax, int schur,
                         const int32_t *rk, uint64_t *Bt, hipStream_t st) {
@@ -72,13 +94,29 @@ hipError_t enqueue_gemm(uint64_t *C, int64_t sc, const uint64_t *Am, int64_t sa,
         const int64_t sbt = (kc + 63) / 64;
         hipError_t e = launch_transpose(Bsrc, sb, kmrows, br, cw, nw, kc, Bt, sbt, rk, st);
         if (e != hipSuccess) return e;
+        int32_t *plog = nullptr;
+        ProfRec rec{};
+        const bool prof = ctx && ctx->plog && (int64_t)ctx->recs.size() < ctx->plog_cap;
+        if (prof) {
+            rec.slot = (int)ctx->recs.size();
+            rec.ncols = 64 * nw;
+            rec.a = pool_event(ctx, 2 * (size_t)rec.slot);
+            rec.b = pool_event(ctx, 2 * (size_t)rec.slot + 1);
+            if (!rec.a || !rec.b) return hipErrorOutOfMemory;
+            plog = ctx->plog + 2 * rec.slot;
+            if ((e = hipEventRecord(rec.a, st)) != hipSuccess) return e;
+        }
         if (schur == GF2_SCHUR_MFMA)
             e = launch_gemm_mfma(C, sc, Am, sa, m, crows, aw + k0 / 64, cw, nw, Bt, sbt, kc, br,
-                                 kmrows, rk, st);
+                                 kmrows, rk, plog, st);
         else
             e = launch_gemm_xor(C, sc, Am, sa, m, crows, aw + k0 / 64, cw, nw, Bt, sbt, kc, br,
-                                kmrows, rk, st);
+                                kmrows, rk, plog, st);
         if (e != hipSuccess) return e;
+        if (prof) {
+            if ((e = hipEventRecord(rec.b, st)) != hipSuccess) return e;
+            ctx->recs.push_back(rec);
+        }
     }
     return hipSuccess;
 }
@@ -97,12 +135,17 @@ size_t gemm_bt_words(int nw, int kmax) {
 // The recursion, run either to size the workspace (dry) or to launch.
 struct PlsDriver {
     bool dry = true;
+    gf2_ctx *ctx = nullptr;
     uint64_t *A = nullptr;
     int64_t stride = 0;
     int m = 0, n = 0, nb = 0;
     gf2_sched s{};
     int32_t *rk = nullptr, *P = nullptr, *Q = nullptr, *info = nullptr;
+    const uint64_t *linv = nullptr;   // L^{-1} rows inside the panel record
     uint64_t *Bt = nullptr;
+    uint64_t *Bbuf = nullptr;         // staged pivot rows, 64 x bstride words
+    int64_t bstride = 0;
+    int cus = 256;
     size_t bt_words = 0;   // capacity (launch) or requirement (dry)
     hipStream_t st = nullptr;
     hipError_t err = hipSuccess;
@@ -119,8 +162,8 @@ struct PlsDriver {
             bt_words = std::max(bt_words, gemm_bt_words(nw, kmax));
             return;
         }
-        chk(enqueue_gemm(A, stride, A, stride, A, stride, m, m, crows, aw, cw, nw, brows, kmax,
-                         s.schur, rk, Bt, st));
+        chk(enqueue_gemm(ctx, A, stride, A, stride, A, stride, m, m, crows, aw, cw, nw, brows,
+                         kmax, s.schur, rk, Bt, st));
     }
 
     // rows [rk[ib] + a, min(rk[ie], rk[ib] + a + sz)) <- L^{-1} rows, L's block
@@ -141,23 +184,21 @@ struct PlsDriver {
     }
 
     // MMPF base case on word columns [wb, wb + nwd): 64-column panels, each
-    // followed by the triangular solve of its pivot rows and the table update of
-    // the rows below, on the block's remaining columns.
+    // followed by the table-driven solve of its pivot rows and update of the
+    // rows below, on the block's remaining columns.
     void base(int wb, int nwd) {
+        if (dry) bstride = std::max<int64_t>(bstride, nwd - 1);
         for (int p = 0; p < nwd; p++) {
             const int wc = wb + p;
-            if (!dry) chk(launch_leaf(A, stride, m, n, wc, rk, wc, P, Q, info, st));
-            if (p + 1 < nwd && !dry) {
-                chk(launch_trsm_base(A, stride, A, stride, m, row_range(wc, wc + 1, 0, 64), wc,
-                                     wc + 1, wb + nwd, rk, 1, st));
-                chk(launch_table_update(A, stride, m, wc, rk, wc, wc + 1, wb + nwd, s.k, s.tables,
-                                        st));
-            }
-        }
-        for (int p = nwd - 2; p >= 0; p--)
+            const bool upd = p + 1 < nwd;
             if (!dry)
-                chk(launch_compress_shift(A, stride, m, 64 * (wb + p), 64, rk, wb + p, wb + p + 1,
-                                          wb + nwd, st));
+                chk(launch_leaf(A, stride, m, n, wc, rk, wc, P, Q, info, upd ? Bbuf : nullptr,
+                                bstride, wc + 1, wb + nwd, st));
+            if (upd && !dry)
+                chk(launch_table_update(A, stride, m, wc, rk, wc, wc + 1, wb + nwd, s.k, s.tables,
+                                        linv, Bbuf, bstride, 2 * cus, st));
+        }
+        if (!dry) chk(launch_compress_chain(A, stride, m, wb, nwd, rk, st));
     }
 
     void node(int wb, int nwd) {
@@ -185,8 +226,9 @@ struct PlsDriver {
 };
 
 struct PlsLayout {
-    size_t rk_off, info_off, bt_off, total;
+    size_t rk_off, info_off, bt_off, bb_off, total;
     size_t bt_words;
+    int64_t bstride;
 };
 
 PlsLayout pls_layout(int64_t m, int64_t n, const gf2_sched &s) {
@@ -206,6 +248,9 @@ PlsLayout pls_layout(int64_t m, int64_t n, const gf2_sched &s) {
     L.bt_off = off;
     L.bt_words = d.bt_words;
     off = align_up(off + d.bt_words * 8);
+    L.bb_off = off;
+    L.bstride = std::max<int64_t>(d.bstride, 1);
+    off = align_up(off + (size_t)64 * L.bstride * 8);
     L.total = off;
     return L;
 }
@@ -238,7 +283,45 @@ int gf2_ctx_create(gf2_ctx **out, int device) {
     return GF2_OK;
 }
 
-void gf2_ctx_destroy(gf2_ctx *ctx) { delete ctx; }
+void gf2_ctx_destroy(gf2_ctx *ctx) {
+    if (!ctx) return;
+    for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+int gf2_prof_enable(gf2_ctx *ctx, int32_t *dev_log, int64_t log_slots) {
+    if (!ctx) return GF2_E_ARG;
+    if (dev_log && log_slots <= 0) return GF2_E_ARG;
+    ctx->plog = dev_log;
+    ctx->plog_cap = dev_log ? log_slots : 0;
+    ctx->recs.clear();
+    return GF2_OK;
+}
+
+int gf2_prof_read(gf2_ctx *ctx, gf2_prof_stats *out) {
+    if (!ctx || !out) return GF2_E_ARG;
+    out->launches = 0;
+    out->total_ms = 0.0;
+    out->total_ops = 0.0;
+    if (ctx->recs.empty()) return GF2_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return GF2_E_HIP;
+    if (hipEventSynchronize(ctx->recs.back().b) != hipSuccess) return GF2_E_HIP;
+    std::vector<int32_t> log(2 * ctx->recs.size());
+    if (hipMemcpy(log.data(), ctx->plog, log.size() * sizeof(int32_t), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return GF2_E_HIP;
+    for (const ProfRec &r : ctx->recs) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) != hipSuccess) return GF2_E_HIP;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return GF2_E_HIP;
+        out->launches += 1;
+        out->total_ms += ms;
+        out->total_ops += 2.0 * (double)log[2 * r.slot] * (double)r.ncols *
+                          (double)log[2 * r.slot + 1];
+    }
+    ctx->recs.clear();
+    return GF2_OK;
+}
 
 const char *gf2_status_str(int status) {
     switch (status) {
@@ -281,6 +364,7 @@ int gf2_pls(gf2_ctx *ctx, gf2_mat A, int32_t *P, int32_t *Q, int32_t *rank, cons
     char *base = (char *)ws;
     PlsDriver d;
     d.dry = false;
+    d.ctx = ctx;
     d.A = A.words;
     d.stride = A.stride;
     d.m = (int)A.m;
@@ -291,6 +375,10 @@ int gf2_pls(gf2_ctx *ctx, gf2_mat A, int32_t *P, int32_t *Q, int32_t *rank, cons
     d.info = (int32_t *)(base + L.info_off);
     d.Bt = (uint64_t *)(base + L.bt_off);
     d.bt_words = L.bt_words;
+    d.Bbuf = (uint64_t *)(base + L.bb_off);
+    d.bstride = L.bstride;
+    d.linv = (const uint64_t *)(base + L.info_off + panel_info_linv_offset());
+    d.cus = ctx->cus;
     d.P = P;
     d.Q = Q;
     d.st = st;
@@ -330,6 +418,7 @@ RrefLayout rref_layout(int64_t m, int64_t n) {
 }
 
 struct UpperSolve {
+    gf2_ctx *ctx;
     uint64_t *X;
     int64_t sx;
     const uint64_t *U;
@@ -353,7 +442,7 @@ struct UpperSolve {
         const int h = (sz / 64 / 2) * 64;
         solve(a + h, sz - h);
         if (a + h < r)
-            chk(enqueue_gemm(X, sx, U, su, X, sx, r, r, row_range(-1, -1, a, h), (a + h) / 64, 0,
+            chk(enqueue_gemm(ctx, X, sx, U, su, X, sx, r, r, row_range(-1, -1, a, h), (a + h) / 64, 0,
                              nwx, row_range(-1, -1, a + h, sz - h), sz - h, GF2_SCHUR_MFMA, rr,
                              Bt, st));
         solve(a, h);
@@ -400,6 +489,7 @@ extern "C" int gf2_rref(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int
                                    Xc, L.sx, st));
         if (nwx > 0) {
             UpperSolve us;
+            us.ctx = ctx;
             us.X = Xc; us.sx = L.sx; us.U = Uc; us.su = L.su; us.r = r; us.nwx = nwx;
             us.rr = (const int32_t *)(base + L.rr); us.Bt = (uint64_t *)(base + L.bt); us.st = st;
             us.solve(0, (r + 63) / 64 * 64);
@@ -452,10 +542,10 @@ int gf2_addmul(gf2_ctx *ctx, gf2_mat C, gf2_mat A, gf2_mat B, int variant, void 
         RowRange cr = row_range(-1, -1, 0, kINF);
         if (variant == GF2_SCHUR_MFMA)
             GF2_TRY(launch_gemm_mfma(C.words, C.stride, A.words, A.stride, m, cr, k0 / 64, 0, nw, Bt,
-                                     sbt, kc, br, K, rk, st));
+                                     sbt, kc, br, K, rk, nullptr, st));
         else
             GF2_TRY(launch_gemm_xor(C.words, C.stride, A.words, A.stride, m, cr, k0 / 64, 0, nw, Bt,
-                                    sbt, kc, br, K, rk, st));
+                                    sbt, kc, br, K, rk, nullptr, st));
     }
     return GF2_OK;
 }

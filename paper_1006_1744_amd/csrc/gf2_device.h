@@ -1,0 +1,88 @@
+// Device helpers shared by the gfx950 kernels: wave-level bit matrix
+// operations on 64 x 64 blocks (one 64-bit row per lane) and the LDS tables of
+// row combinations used by every table-driven update.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gf2 {
+
+__device__ inline uint64_t readlane64(uint64_t v, int l) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t shfl_xor64(uint64_t v, int mask) {
+    int lo = __shfl_xor((int)(uint32_t)v, mask);
+    int hi = __shfl_xor((int)(uint32_t)(v >> 32), mask);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// 64 x 64 bit transpose across a wave: lane i holds row i on entry and column i
+// on exit.  Six butterfly stages, each exchanging the s-bit of the row and
+// column indices between lanes i and i ^ s.
+__device__ inline uint64_t transpose64(uint64_t v, int lane) {
+    const uint64_t hi_mask[6] = {0xFFFFFFFF00000000ull, 0xFFFF0000FFFF0000ull,
+                                 0xFF00FF00FF00FF00ull, 0xF0F0F0F0F0F0F0F0ull,
+                                 0xCCCCCCCCCCCCCCCCull, 0xAAAAAAAAAAAAAAAAull};
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        const int s = 32 >> k;
+        const uint64_t mh = hi_mask[k];
+        uint64_t p = shfl_xor64(v, s);
+        if ((lane & s) == 0)
+            v = (v & ~mh) | ((p & ~mh) << s);
+        else
+            v = (v & mh) | ((p & mh) >> s);
+    }
+    return v;
+}
+
+// Inverse of a 64 x 64 unit triangular matrix T given by the rows in LDS `rows`
+// (only the strictly lower part, bits < i of row i, is read when lower != 0;
+// only the strictly upper part otherwise).  Lane j solves T x = e_j by
+// substitution, one row per step, so every step is a parity of an AND; the
+// result is returned as rows (lane i = row i of T^{-1}).
+__device__ inline uint64_t tri_inverse64(const uint64_t *rows, int lane, bool lower) {
+    uint64_t x = 0;
+    if (lower) {
+        for (int i = 0; i < 64; i++) {
+            const uint64_t li = rows[i] & ((1ull << i) - 1);
+            uint64_t b = (uint64_t)((__popcll(li & x) & 1) ^ (i == lane));
+            x |= b << i;
+        }
+    } else {
+        for (int i = 63; i >= 0; i--) {
+            const uint64_t ui = i == 63 ? 0ull : (rows[i] & (~0ull << (i + 1)));
+            uint64_t b = (uint64_t)((__popcll(ui & x) & 1) ^ (i == lane));
+            x |= b << i;
+        }
+    }
+    return transpose64(x, lane);
+}
+
+// Tables of all combinations of groups of k consecutive rows: for group g,
+// T[(g * 2^k + e) * TW + w] = XOR of rows g*k + u with bit u of e set (rows
+// past nrows read as zero), word w of a TW-word tile.  Built by doubling, one
+// level per barrier: entries [2^l, 2^(l+1)) = entries [0, 2^l) + row g*k + l.
+// rows: LDS [>= ng*k][TW].  All threads of the block must call it.
+__device__ inline void build_group_tables(const uint64_t *rows, int nrows, int k, int ng,
+                                          uint64_t *T, int TW, int tid, int nthr) {
+    const int esz = 1 << k;
+    for (int e = tid; e < ng * TW; e += nthr) T[(e / TW) * esz * TW + (e % TW)] = 0ull;
+    __syncthreads();
+    for (int l = 0; l < k; l++) {
+        const int half = 1 << l;
+        for (int e = tid; e < ng * half * TW; e += nthr) {
+            const int w = e % TW, idx = (e / TW) % half, g = e / (TW * half);
+            const int row = g * k + l;
+            const uint64_t add = row < nrows ? rows[row * TW + w] : 0ull;
+            T[((size_t)g * esz + half + idx) * TW + w] = T[((size_t)g * esz + idx) * TW + w] ^ add;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace gf2

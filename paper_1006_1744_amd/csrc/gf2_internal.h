@@ -53,9 +53,13 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st)
 // Writes rk[b + 1], P and Q at the pivot slots, and the moved-row list.
 // Also moves the other words of the pivot rows (the full-row swaps).
 // `info` is a device scratch record of panel_info_bytes() bytes.
+// The pivot rows' words on [bw_lo, bw_hi) are copied (after the swaps) into
+// Bbuf (row t at Bbuf + t * bstride) when Bbuf is non-null.
 hipError_t launch_leaf(uint64_t *A, int64_t stride, int m, int n, int wc, int32_t *rk, int b,
-                       int32_t *P, int32_t *Q, int32_t *info, hipStream_t st);
+                       int32_t *P, int32_t *Q, int32_t *info, uint64_t *Bbuf, int64_t bstride,
+                       int bw_lo, int bw_hi, hipStream_t st);
 size_t panel_info_bytes();
+size_t panel_info_linv_offset();
 
 // X <- L^{-1} X for at most 64 rows `rows` of X (matrix A) with the unit lower
 // triangular L taken from word column lw of the same rows of matrix Lm (bit i
@@ -65,18 +69,26 @@ hipError_t launch_trsm_base(uint64_t *A, int64_t stride, const uint64_t *Lm, int
                             RowRange rows, int lw, int w_lo, int w_hi, const int32_t *rk,
                             int lower, hipStream_t st);
 
-// Table-driven update after a panel (Section 4.1: MakeTable1 / AddRowsFromTable):
-// rows [rk[b+1], m) on word columns [w_lo, w_hi) receive L * U, where L is the
-// row's panel word (compressed multipliers) and U the r = rk[b+1]-rk[b] pivot
-// rows on the same columns.  k bits per table, `tables` tables per pass.
+// Table-driven update after a panel (Section 4.1: MakeTable1 / AddRowsFromTable)
+// on word columns [w_lo, w_hi): the panel's pivot rows become U = L^{-1} B and
+// every row below adds l U, l its compressed panel word; B (the pivot rows as
+// staged by launch_leaf) is read from Bbuf, L^{-1} from `linv` (64 rows).
+// k bits per table, `tables` tables per pass over the rows.
 hipError_t launch_table_update(uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk,
-                               int b, int w_lo, int w_hi, int k, int tables, hipStream_t st);
+                               int b, int w_lo, int w_hi, int k, int tables, const uint64_t *linv,
+                               const uint64_t *Bbuf, int64_t bstride, int target_blocks,
+                               hipStream_t st);
 
 // Move the second block's L columns next to the first block's (Section 5,
 // final "compress L"): node at column c0 (multiple of 64), split n0 columns,
 // ranks r0 = rk[b1] - rk[b0], r1 = rk[b2] - rk[b1].
 hipError_t launch_compress_shift(uint64_t *A, int64_t stride, int m, int c0, int n0,
                                  const int32_t *rk, int b0, int b1, int b2, hipStream_t st);
+
+// All shifts of an MMPF block of nwd panels at word wb (splits after each panel),
+// innermost first.
+hipError_t launch_compress_chain(uint64_t *A, int64_t stride, int m, int wb, int nwd,
+                                 const int32_t *rk, hipStream_t st);
 
 // P[i] = i for i >= r, Q[i] = i for r <= i < n, *rank = r, with r = rk[nb].
 hipError_t launch_finalize(int32_t *P, int32_t *Q, int32_t *rank, const int32_t *rk, int nb,
@@ -92,14 +104,15 @@ hipError_t launch_transpose(const uint64_t *B, int64_t sb, int m, RowRange brows
 // C[rows, words w_lo..w_lo+nw) ^= A[rows, K bits from word aw] * B, with B given
 // transposed in Bt (64*nw rows of kmax bits, zero past K).  K is the length of
 // krows evaluated with kmrows as the default end.
+// prof (nullable): the kernel stores its M and K there (timing diagnostics).
 hipError_t launch_gemm_xor(uint64_t *C, int64_t sc, const uint64_t *A, int64_t sa, int m,
                            RowRange rows, int aw, int w_lo, int nw, const uint64_t *Bt,
                            int64_t sbt, int kmax, RowRange krows, int kmrows, const int32_t *rk,
-                           hipStream_t st);
+                           int32_t *prof, hipStream_t st);
 hipError_t launch_gemm_mfma(uint64_t *C, int64_t sc, const uint64_t *A, int64_t sa, int m,
                             RowRange rows, int aw, int w_lo, int nw, const uint64_t *Bt,
                             int64_t sbt, int kmax, RowRange krows, int kmrows, const int32_t *rk,
-                            hipStream_t st);
+                            int32_t *prof, hipStream_t st);
 
 // RREF helpers (k_rref.hip)
 hipError_t launch_zero_rows(uint64_t *X, int64_t sx, int rows, int words, hipStream_t st);

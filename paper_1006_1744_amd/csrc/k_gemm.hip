@@ -80,19 +80,22 @@ __global__ __launch_bounds__(256) void gemm_xor_kernel(uint64_t *C, int64_t sc, 
                                                        int64_t sa, int m, RowRange rows, int aw,
                                                        int w_lo, int nw, const uint64_t *Bt,
                                                        int64_t sbt, int nkw, RowRange krows,
-                                                       int kmrows, const int32_t *rk) {
+                                                       int kmrows, const int32_t *rk,
+                                                       int32_t *prof) {
     __shared__ uint64_t sA[GX_TM][GX_LD];
     __shared__ uint64_t sB[GX_TNW * 64][GX_LD];
     int r0, r1;
     eval_range(rk, m, rows, r0, r1);
     const int M = r1 - r0;
-    if (M <= 0) return;
-    {
-        int k0, k1;
-        eval_range(rk, kmrows, krows, k0, k1);
-        nkw = min(nkw, (k1 - k0 + 63) / 64);
-        if (nkw <= 0) return;
+    int k0, k1;
+    eval_range(rk, kmrows, krows, k0, k1);
+    if (prof && blockIdx.x == 0 && threadIdx.x == 0) {
+        prof[0] = M;
+        prof[1] = k1 - k0;
     }
+    if (M <= 0) return;
+    nkw = min(nkw, (k1 - k0 + 63) / 64);
+    if (nkw <= 0) return;
     const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
     const int lane = tid & 63;
     const int tiles_m = (M + GX_TM - 1) / GX_TM;
@@ -184,14 +187,14 @@ __global__ __launch_bounds__(256) void gemm_xor_kernel(uint64_t *C, int64_t sc, 
 hipError_t launch_gemm_xor(uint64_t *C, int64_t sc, const uint64_t *A, int64_t sa, int m,
                            RowRange rows, int aw, int w_lo, int nw, const uint64_t *Bt,
                            int64_t sbt, int kmax, RowRange krows, int kmrows, const int32_t *rk,
-                           hipStream_t st) {
+                           int32_t *prof, hipStream_t st) {
     int nkw = (kmax + 63) / 64;
     if (nw <= 0 || nkw <= 0) return hipSuccess;
     int64_t tiles = (int64_t)((m + GX_TM - 1) / GX_TM) * ((nw + GX_TNW - 1) / GX_TNW);
     int64_t blocks = tiles < 2048 ? tiles : 2048;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(gemm_xor_kernel, dim3((unsigned)blocks), dim3(256), 0, st, C, sc, A, sa, m,
-                       rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk);
+                       rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof);
     return hipGetLastError();
 }
 

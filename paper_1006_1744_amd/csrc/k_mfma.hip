@@ -28,19 +28,21 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(uint64_t *C, int64_t sc,
                                                         RowRange rows, int aw, int w_lo, int nw,
                                                         const uint64_t *Bt, int64_t sbt, int nkw,
                                                         RowRange krows, int kmrows,
-                                                        const int32_t *rk) {
+                                                        const int32_t *rk, int32_t *prof) {
     __shared__ uint64_t sA[GM_TM][GM_LD];
     __shared__ uint64_t sB[GM_TN][GM_LD];
     int r0, r1;
     eval_range(rk, m, rows, r0, r1);
     const int M = r1 - r0;
-    if (M <= 0) return;
-    {
-        int k0, k1;
-        eval_range(rk, kmrows, krows, k0, k1);
-        nkw = min(nkw, (k1 - k0 + 63) / 64);
-        if (nkw <= 0) return;
+    int k0, k1;
+    eval_range(rk, kmrows, krows, k0, k1);
+    if (prof && blockIdx.x == 0 && threadIdx.x == 0) {
+        prof[0] = M;
+        prof[1] = k1 - k0;
     }
+    if (M <= 0) return;
+    nkw = min(nkw, (k1 - k0 + 63) / 64);
+    if (nkw <= 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;          // 2 x 2 waves, 64 x 64 each
     const int li = lane & 31, lg = lane >> 5;         // row in block, K half
@@ -130,14 +132,14 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(uint64_t *C, int64_t sc,
 hipError_t launch_gemm_mfma(uint64_t *C, int64_t sc, const uint64_t *A, int64_t sa, int m,
                             RowRange rows, int aw, int w_lo, int nw, const uint64_t *Bt,
                             int64_t sbt, int kmax, RowRange krows, int kmrows, const int32_t *rk,
-                            hipStream_t st) {
+                            int32_t *prof, hipStream_t st) {
     int nkw = (kmax + 63) / 64;
     if (nw <= 0 || nkw <= 0) return hipSuccess;
     int64_t tiles = (int64_t)((m + GM_TM - 1) / GM_TM) * ((nw * 64 + GM_TN - 1) / GM_TN);
     int64_t blocks = tiles < 2048 ? tiles : 2048;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(gemm_mfma_kernel, dim3((unsigned)blocks), dim3(256), 0, st, C, sc, A, sa, m,
-                       rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk);
+                       rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof);
     return hipGetLastError();
 }
 

@@ -17,12 +17,15 @@
 //    scans the rows past the window in order and stops at the first hit.
 // The final pass (panel_post) applies the pending tables to rows >= F and the
 // "compress L" column swaps of the panel, and moves the pivot rows' other words.
+#include <stddef.h>
+
+#include "gf2_device.h"
 #include "gf2_internal.h"
 
 namespace gf2 {
 
 constexpr int LEAF_THREADS = 256;
-constexpr int LEAF_H = 4;
+constexpr int LEAF_H = 2;
 constexpr int LEAF_W = 64 * LEAF_H;
 
 // Per-panel record written by the search kernel and read by panel_post.
@@ -33,14 +36,9 @@ struct PanelInfo {
     int32_t compress;// non-zero if some pivot column differs from its index
     int32_t q[64];   // pivot columns relative to the panel
     uint64_t u[64];  // pivot rows' panel words when chosen (reduced by earlier pivots)
+    uint64_t linv[64];  // rows of L^{-1} for the panel's r x r unit lower triangle
     int32_t moved[kMovedInts];
 };
-
-__device__ inline uint64_t shfl64(uint64_t v, int src) {
-    int lo = __shfl((int)(uint32_t)v, src);
-    int hi = __shfl((int)(uint32_t)(v >> 32), src);
-    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-}
 
 __device__ inline int shfl32(int v, int src) { return __shfl(v, src); }
 
@@ -81,12 +79,28 @@ __device__ inline uint64_t apply_tables(uint64_t x, const int32_t *q, int ta, in
     return x;
 }
 
-// value of window register h (dynamic, wave-uniform h)
-__device__ inline uint64_t wsel(const uint64_t (&x)[LEAF_H], int h) {
-    uint64_t v = x[0];
+// Entry (h, l) of the window, h and l wave-uniform; every register is read
+// with a static index so the window stays in VGPRs.
+__device__ inline uint64_t window_get(const uint64_t (&x)[LEAF_H], int h, int l) {
+    uint64_t v = 0;
 #pragma unroll
-    for (int k = 1; k < LEAF_H; k++) if (h == k) v = x[k];
+    for (int k = 0; k < LEAF_H; k++) {
+        uint64_t t = readlane64(x[k], l);
+        v = (h == k) ? t : v;
+    }
     return v;
+}
+
+// Wave-0 bookkeeping of a new pivot t (wave-uniform arguments): the pivot's
+// multipliers in pivot order, Lc = (bit q_s of the pivot word for s < t), give
+// row t of the panel's unit lower triangle L; lane j keeps column j of L^{-1}
+// and extends it by one substitution step.
+__device__ inline void note_pivot(int t, int col, uint64_t pw, int lane, int &lq,
+                                  uint64_t &linvc) {
+    const uint64_t Lc = __ballot(lane < t && ((pw >> lq) & 1ull));
+    if (lane == t) lq = col;
+    const uint64_t bit = (uint64_t)((__popcll(Lc & linvc) & 1) ^ (lane == t ? 1 : 0));
+    linvc |= bit << t;
 }
 
 __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
@@ -97,7 +111,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
     __shared__ int32_t sPrel[64];
     __shared__ uint64_t sT[8][256];   // pending pivots [pa, t), for rows >= F
     __shared__ uint64_t sE[8][256];   // pivots of the last epoch, for rows in [window end, F)
-    __shared__ int s_t, s_c, s_F, s_pa, s_brk, s_far, s_tab_lo, s_tab_hi;
+    __shared__ int s_t, s_c, s_F, s_pa, s_brk, s_far, s_tab_lo, s_tab_hi, s_epochs;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int R = rk[b];
@@ -105,19 +119,28 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
     const int nc = min(64, n - 64 * wc);
     uint64_t *col = A + (int64_t)R * stride + wc;
     const int NOHIT = 0x7fffffff;
+    // wave 0 state kept across rounds
+    int lq = 0;              // lane s: panel column of pivot s
+    uint64_t linvc = 0;      // lane j: column j of L^{-1}
+    int og[LEAF_H];          // original offset of the row in each window entry
+    bool simple = true;      // one window, no far search: moves read off og[]
 
     if (tid == 0) {
         s_t = 0; s_c = 0; s_F = 0; s_pa = 0; s_tab_lo = -1; s_tab_hi = -1; s_brk = 0;
-        s_far = NOHIT;
+        s_far = NOHIT; s_epochs = 0;
     }
+#pragma unroll
+    for (int h = 0; h < LEAF_H; h++) og[h] = lane + 64 * h;
     __syncthreads();
 
     // Invariant at the top of each round: rows at offsets [t, F) are reduced by
     // every pivot found so far; rows >= F are reduced by pivots [0, pa) only.
     while (true) {
         const int t = s_t, c = s_c, F = s_F, pa = s_pa, tl = s_tab_lo, th = s_tab_hi;
+        const int epochs = s_epochs;
         __syncthreads();
         if (mrem <= 0 || c >= nc || t >= mrem) break;
+        if (epochs > 0) simple = false;
         const bool need_tab = F < mrem && t > pa && (tl != pa || th != t);
         if (need_tab) build_tables(sU, sQ, pa, t, sT, tid, LEAF_THREADS);
         __syncthreads();
@@ -128,11 +151,12 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
             bool valid[LEAF_H];
 #pragma unroll
             for (int h = 0; h < LEAF_H; h++) {
-                int o = ts + lane + 64 * h;
+                const int o = ts + lane + 64 * h;
                 valid[h] = o < mrem;
                 uint64_t v = valid[h] ? col[(int64_t)o * stride] : 0;
                 if (valid[h] && o >= F && t > pa) v = apply_tables(v, sQ, pa, t, sT);
                 x[h] = v;
+                og[h] = o;
             }
             int tt = t, cc = c, brk = 0;
             while (cc < nc && tt < mrem) {
@@ -140,9 +164,9 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
                 int fe = -1;
 #pragma unroll
                 for (int h = 0; h < LEAF_H; h++) {
-                    int e = lane + 64 * h;
-                    bool cand = valid[h] && e >= es && ((x[h] >> cc) & 1);
-                    uint64_t bal = __ballot(cand);
+                    const int e = lane + 64 * h;
+                    const bool cand = valid[h] && e >= es && ((x[h] >> cc) & 1);
+                    const uint64_t bal = __ballot(cand);
                     if (fe < 0 && bal) fe = 64 * h + __ffsll((unsigned long long)bal) - 1;
                 }
                 if (fe < 0) {
@@ -150,13 +174,24 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
                     brk = 1;
                     break;
                 }
-                const int he = fe >> 6, le = fe & 63, hs = es >> 6, ls = es & 63;
-                uint64_t pw = shfl64(wsel(x, he), le);
-                uint64_t sw = shfl64(wsel(x, hs), ls);
+                const int he = fe >> 6, le = fe & 63;
+                const uint64_t pw = window_get(x, he, le);
+                if (fe != es) {
+                    const int hs = es >> 6, ls = es & 63;
+                    const uint64_t sw = window_get(x, hs, ls);
+                    int og_e = 0, og_s = 0;
 #pragma unroll
-                for (int h = 0; h < LEAF_H; h++) {
-                    if (h == hs && lane == ls) x[h] = pw;
-                    if (h == he && lane == le) x[h] = sw;
+                    for (int h = 0; h < LEAF_H; h++) {
+                        const int ve = __builtin_amdgcn_readlane(og[h], le);
+                        const int vs = __builtin_amdgcn_readlane(og[h], ls);
+                        og_e = (h == he) ? ve : og_e;
+                        og_s = (h == hs) ? vs : og_s;
+                    }
+#pragma unroll
+                    for (int h = 0; h < LEAF_H; h++) {
+                        if (h == hs && lane == ls) { x[h] = pw; og[h] = og_e; }
+                        if (h == he && lane == le) { x[h] = sw; og[h] = og_s; }
+                    }
                 }
                 if (lane == 0) {
                     sU[tt] = pw;
@@ -165,24 +200,27 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
                     P[R + tt] = R + ts + fe;
                     Q[R + tt] = 64 * wc + cc;
                 }
+                note_pivot(tt, cc, pw, lane, lq, linvc);
                 const uint64_t above = cc == 63 ? 0ull : (~0ull << (cc + 1));
+                const uint64_t add = pw & above;
 #pragma unroll
                 for (int h = 0; h < LEAF_H; h++) {
-                    int e = lane + 64 * h;
-                    if (valid[h] && e > es && ((x[h] >> cc) & 1)) x[h] ^= pw & above;
+                    const int e = lane + 64 * h;
+                    if (valid[h] && e > es && ((x[h] >> cc) & 1)) x[h] ^= add;
                 }
                 tt++;
                 cc++;
             }
 #pragma unroll
             for (int h = 0; h < LEAF_H; h++) {
-                int o = ts + lane + 64 * h;
+                const int o = ts + lane + 64 * h;
                 if (valid[h]) col[(int64_t)o * stride] = x[h];
             }
             if (lane == 0) {
                 s_t = tt;
                 s_c = cc;
                 s_brk = brk;
+                s_epochs = epochs + 1;
                 const int nF = max(F, min(ts + LEAF_W, mrem));
                 s_F = nF;
                 if (nF >= mrem) s_pa = tt;   // no row is left past the frontier
@@ -204,6 +242,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
         // Far search: no window row has a one in column c1.  Scan the rows past
         // the window in order, bringing rows >= F up to date, and stop after the
         // first block-sized chunk holding a hit.
+        simple = false;
         const int F2 = s_F, pa2 = s_pa, tl2 = s_tab_lo, th2 = s_tab_hi;
         __syncthreads();
         const bool need2 = F2 < mrem && t1 > pa2 && (tl2 != pa2 || th2 != t1);
@@ -248,6 +287,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
             Q[R + t1] = 64 * wc + c1;
         }
         __syncthreads();
+        if (wave == 0) note_pivot(t1, c1, sU[t1], lane, lq, linvc);
         {
             // rows after f up to the new frontier may hold a one in column c1
             const uint64_t pw = sU[t1];
@@ -262,52 +302,73 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
             s_t = t1 + 1;
             s_c = c1 + 1;
             s_F = F3;
-            if (F3 >= mrem) s_pa = t1 + 1;
+            s_pa = F3 >= mrem ? t1 + 1 : pa2;
+            s_epochs = 2;   // moved rows no longer follow from one window
         }
         __syncthreads();
     }
     __syncthreads();
 
-    // Record results and compose the transpositions into moved-row pairs.
     const int r = max(0, min(s_t, mrem));
     if (wave == 0) {
-        // list entries: lane holds entries lane and lane + 64
-        int pos0 = -1, src0 = 0, pos1 = -1, src1 = 0;
-        int nk = 0;
-        for (int s = 0; s < r; s++) {
-            const int a = s, qq = sPrel[s];
-            if (a == qq) continue;
-            uint64_t ba = __ballot(pos0 == a) | 0, ba1 = __ballot(pos1 == a);
-            uint64_t bq = __ballot(pos0 == qq), bq1 = __ballot(pos1 == qq);
-            int ia = ba ? __ffsll((unsigned long long)ba) - 1
-                        : (ba1 ? 64 + __ffsll((unsigned long long)ba1) - 1 : -1);
-            int iq = bq ? __ffsll((unsigned long long)bq) - 1
-                        : (bq1 ? 64 + __ffsll((unsigned long long)bq1) - 1 : -1);
-            int sa = a, sq = qq;
-            if (ia >= 0) sa = ia < 64 ? shfl32(src0, ia) : shfl32(src1, ia - 64);
-            if (iq >= 0) sq = iq < 64 ? shfl32(src0, iq) : shfl32(src1, iq - 64);
-            // position a now holds the row that was at qq, and qq the one at a
-            int slot_a = ia >= 0 ? ia : nk;
-            if (ia < 0) nk++;
-            int slot_q = iq >= 0 ? iq : nk;
-            if (iq < 0) nk++;
-            if (slot_a < 64) { if (lane == slot_a) { pos0 = a; src0 = sq; } }
-            else if (lane == slot_a - 64) { pos1 = a; src1 = sq; }
-            if (slot_q < 64) { if (lane == slot_q) { pos0 = qq; src0 = sa; } }
-            else if (lane == slot_q - 64) { pos1 = qq; src1 = sa; }
-        }
         int32_t *mv = info->moved;
-        if (lane == 0) mv[0] = nk;
-        if (lane < nk) { mv[1 + 2 * lane] = pos0; mv[2 + 2 * lane] = src0; }
-        if (lane + 64 < nk) { mv[1 + 2 * (lane + 64)] = pos1; mv[2 + 2 * (lane + 64)] = src1; }
-    }
-    if (tid < 64) {
-        info->q[tid] = tid < r ? sQ[tid] : tid;
-        info->u[tid] = tid < r ? sU[tid] : 0ull;
+        if (simple) {
+            // one window starting at offset 0: entry e holds the row from og[e]
+            int base_cnt = 0;
+#pragma unroll
+            for (int h = 0; h < LEAF_H; h++) {
+                const int e = lane + 64 * h;
+                const bool mvd = og[h] != e && e < mrem;
+                const uint64_t bal = __ballot(mvd);
+                const int idx = base_cnt + __popcll(bal & ((1ull << lane) - 1));
+                if (mvd) { mv[1 + 2 * idx] = e; mv[2 + 2 * idx] = og[h]; }
+                base_cnt += __popcll(bal);
+            }
+            if (lane == 0) mv[0] = base_cnt;
+        } else {
+            // compose the transpositions (s, sPrel[s]) into (position, source) pairs;
+            // lane holds list entries lane and lane + 64
+            int pos0 = -1, src0 = 0, pos1 = -1, src1 = 0;
+            int nk = 0;
+            for (int s2 = 0; s2 < r; s2++) {
+                const int a = s2, qq = sPrel[s2];
+                if (a == qq) continue;
+                const uint64_t ba = __ballot(pos0 == a), ba1 = __ballot(pos1 == a);
+                const uint64_t bq = __ballot(pos0 == qq), bq1 = __ballot(pos1 == qq);
+                const int ia = ba ? __ffsll((unsigned long long)ba) - 1
+                                  : (ba1 ? 64 + __ffsll((unsigned long long)ba1) - 1 : -1);
+                const int iq = bq ? __ffsll((unsigned long long)bq) - 1
+                                  : (bq1 ? 64 + __ffsll((unsigned long long)bq1) - 1 : -1);
+                int sa = a, sq = qq;
+                if (ia >= 0)
+                    sa = ia < 64 ? __builtin_amdgcn_readlane(src0, ia)
+                                 : __builtin_amdgcn_readlane(src1, ia - 64);
+                if (iq >= 0)
+                    sq = iq < 64 ? __builtin_amdgcn_readlane(src0, iq)
+                                 : __builtin_amdgcn_readlane(src1, iq - 64);
+                // position a now holds the row that was at qq, and qq the one at a
+                const int slot_a = ia >= 0 ? ia : nk;
+                if (ia < 0) nk++;
+                const int slot_q = iq >= 0 ? iq : nk;
+                if (iq < 0) nk++;
+                if (slot_a < 64) { if (lane == slot_a) { pos0 = a; src0 = sq; } }
+                else if (lane == slot_a - 64) { pos1 = a; src1 = sq; }
+                if (slot_q < 64) { if (lane == slot_q) { pos0 = qq; src0 = sa; } }
+                else if (lane == slot_q - 64) { pos1 = qq; src1 = sa; }
+            }
+            if (lane == 0) mv[0] = nk;
+            if (lane < nk) { mv[1 + 2 * lane] = pos0; mv[2 + 2 * lane] = src0; }
+            if (lane + 64 < nk) { mv[1 + 2 * (lane + 64)] = pos1; mv[2 + 2 * (lane + 64)] = src1; }
+        }
+        // L^{-1}: identity past r, then columns -> rows
+        if (lane >= r) linvc = 1ull << lane;
+        info->linv[lane] = transpose64(linvc, lane);
+        info->q[lane] = lane < r ? sQ[lane] : lane;
+        info->u[lane] = lane < r ? sU[lane] : 0ull;
     }
     if (tid == 0) {
         int cmp = 0;
-        for (int s = 0; s < r; s++) cmp |= (sQ[s] != s);
+        for (int s2 = 0; s2 < r; s2++) cmp |= (sQ[s2] != s2);
         info->r = r;
         info->F = max(0, min(s_F, mrem));
         info->pa = min(s_pa, r);
@@ -323,7 +384,7 @@ constexpr int SWAP_COLS = 64;
 
 __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
     uint64_t *A, int64_t stride, int m, int wc, int nwords, const int32_t *rk, int b,
-    const PanelInfo *info, int nfin) {
+    const PanelInfo *info, int nfin, uint64_t *Bbuf, int64_t bstride, int bw_lo, int bw_hi) {
     __shared__ uint64_t sT[8][256];
     __shared__ uint64_t sU[64];
     __shared__ int32_t sQ[64];
@@ -366,20 +427,30 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
     // moved rows, other word columns: stage every source, then write
     const int32_t *mv = info->moved;
     const int nk = mv[0];
-    if (nk == 0) return;
     const int w = (blockIdx.x - nfin) * SWAP_COLS + (tid & (SWAP_COLS - 1));
     const int part = tid / SWAP_COLS;          // POST_THREADS / SWAP_COLS parts
     const bool act = w < nwords && w != wc;
-    for (int k = part; k < nk; k += POST_THREADS / SWAP_COLS)
-        stage[k][tid & (SWAP_COLS - 1)] = act ? A[(int64_t)(R + mv[2 + 2 * k]) * stride + w] : 0;
-    __syncthreads();
-    if (act)
+    if (nk > 0) {
         for (int k = part; k < nk; k += POST_THREADS / SWAP_COLS)
-            A[(int64_t)(R + mv[1 + 2 * k]) * stride + w] = stage[k][tid & (SWAP_COLS - 1)];
+            stage[k][tid & (SWAP_COLS - 1)] =
+                act ? A[(int64_t)(R + mv[2 + 2 * k]) * stride + w] : 0;
+        __syncthreads();
+        if (act)
+            for (int k = part; k < nk; k += POST_THREADS / SWAP_COLS)
+                A[(int64_t)(R + mv[1 + 2 * k]) * stride + w] = stage[k][tid & (SWAP_COLS - 1)];
+    }
+    // the pivot rows' words on [bw_lo, bw_hi), for the update that follows
+    if (Bbuf != nullptr && bw_hi > bw_lo) {
+        __syncthreads();
+        if (w >= bw_lo && w < bw_hi)
+            for (int t = part; t < r; t += POST_THREADS / SWAP_COLS)
+                Bbuf[(int64_t)t * bstride + (w - bw_lo)] = A[(int64_t)(R + t) * stride + w];
+    }
 }
 
 hipError_t launch_leaf(uint64_t *A, int64_t stride, int m, int n, int wc, int32_t *rk, int b,
-                       int32_t *P, int32_t *Q, int32_t *infobuf, hipStream_t st) {
+                       int32_t *P, int32_t *Q, int32_t *infobuf, uint64_t *Bbuf,
+                       int64_t bstride, int bw_lo, int bw_hi, hipStream_t st) {
     PanelInfo *info = reinterpret_cast<PanelInfo *>(infobuf);
     hipLaunchKernelGGL(leaf_search_kernel, dim3(1), dim3(LEAF_THREADS), 0, st, A, stride, m, n,
                        wc, rk, b, P, Q, info);
@@ -391,10 +462,11 @@ hipError_t launch_leaf(uint64_t *A, int64_t stride, int m, int n, int wc, int32_
     if (nfin < 1) nfin = 1;
     int nswap = (nwords + SWAP_COLS - 1) / SWAP_COLS;
     hipLaunchKernelGGL(panel_post_kernel, dim3(nfin + nswap), dim3(POST_THREADS), 0, st, A,
-                       stride, m, wc, nwords, rk, b, info, nfin);
+                       stride, m, wc, nwords, rk, b, info, nfin, Bbuf, bstride, bw_lo, bw_hi);
     return hipGetLastError();
 }
 
 size_t panel_info_bytes() { return sizeof(PanelInfo); }
+size_t panel_info_linv_offset() { return offsetof(PanelInfo, linv); }
 
 }  // namespace gf2

@@ -16,6 +16,7 @@
 //                    pass over the rows.
 // compress_shift_kernel  final "compress L" of Section 5.
 // finalize_kernel    P, Q tails and the rank.
+#include "gf2_device.h"
 #include "gf2_internal.h"
 
 namespace gf2 {
@@ -33,83 +34,50 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st)
 }
 
 // ------------------------------------------------------------------ TRSM
+// X <- T^{-1} X on at most 64 rows: T^{-1} is formed by one wave (column-wise
+// substitution, tri_inverse64), then every output row is a combination of the
+// block's rows: X[i] = sum_j Tinv[i][j] B[j], evaluated with tables of all 16
+// combinations of each 4 consecutive rows (MakeTable with k = 4, Section 3.1)
+// and one table row per group (AddRowsFromTable).
 constexpr int TRSM_THREADS = 256;
 constexpr int TRSM_TW = 16;   // tile words
-constexpr int TRSM_K = 8;
+constexpr int TRSM_K = 4;
+constexpr int TRSM_NG = 64 / TRSM_K;
 
 __global__ __launch_bounds__(TRSM_THREADS) void trsm_base_kernel(
     uint64_t *A, int64_t stride, const uint64_t *Lm, int64_t sl, int m, RowRange rows, int lw,
     int w_lo, int w_hi, const int32_t *rk, int lower) {
-    __shared__ uint64_t sX[64][TRSM_TW];
-    __shared__ uint64_t sT[256][TRSM_TW];
+    __shared__ uint64_t sB[64 * TRSM_TW];
+    __shared__ uint64_t sT[TRSM_NG * (1 << TRSM_K) * TRSM_TW];
     __shared__ uint64_t sL[64];
+    __shared__ uint64_t sInv[64];
     int r0, r1;
     eval_range(rk, m, rows, r0, r1);
     const int nr = min(r1 - r0, 64);
     if (nr <= 1) return;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
     const int w0 = w_lo + blockIdx.x * TRSM_TW;
     const int tw_n = min(TRSM_TW, w_hi - w0);
     if (tw_n <= 0) return;
     for (int e = tid; e < 64 * TRSM_TW; e += TRSM_THREADS) {
         int s = e / TRSM_TW, w = e % TRSM_TW;
-        sX[s][w] = (s < nr && w < tw_n) ? A[(int64_t)(r0 + s) * stride + w0 + w] : 0ull;
+        sB[e] = (s < nr && w < tw_n) ? A[(int64_t)(r0 + s) * stride + w0 + w] : 0ull;
     }
     if (tid < 64) {
-        uint64_t lv = tid < nr ? Lm[(int64_t)(r0 + tid) * sl + lw] : 0ull;
-        uint64_t below = tid == 0 ? 0ull : (~0ull >> (64 - tid));
-        sL[tid] = lower ? (lv & below) : (lv & ~below & ~(1ull << tid));
+        const uint64_t keep = nr == 64 ? ~0ull : ((1ull << nr) - 1);
+        sL[tid] = tid < nr ? (Lm[(int64_t)(r0 + tid) * sl + lw] & keep) : 0ull;
     }
     __syncthreads();
-    const int ng = (nr + TRSM_K - 1) / TRSM_K;
-    for (int gi = 0; gi < ng; gi++) {
-        const int g = lower ? gi : ng - 1 - gi;
-        const int gb = g * TRSM_K, gs = min(TRSM_K, nr - gb);
-        // substitution inside the group
-        if (tid < TRSM_TW) {
-            const int w = tid;
-            if (lower) {
-                for (int u = 1; u < gs; u++) {
-                    uint64_t lv = sL[gb + u];
-                    uint64_t acc = sX[gb + u][w];
-                    for (int v = 0; v < u; v++)
-                        if ((lv >> (gb + v)) & 1) acc ^= sX[gb + v][w];
-                    sX[gb + u][w] = acc;
-                }
-            } else {
-                for (int u = gs - 2; u >= 0; u--) {
-                    uint64_t lv = sL[gb + u];
-                    uint64_t acc = sX[gb + u][w];
-                    for (int v = u + 1; v < gs; v++)
-                        if ((lv >> (gb + v)) & 1) acc ^= sX[gb + v][w];
-                    sX[gb + u][w] = acc;
-                }
-            }
-        }
-        __syncthreads();
-        const bool more = lower ? (gb + gs < nr) : (gb > 0);
-        if (!more) break;
-        // tabulate the group's combinations
-        for (int e = tid; e < (1 << gs) * TRSM_TW; e += TRSM_THREADS) {
-            int comb = e / TRSM_TW, w = e % TRSM_TW;
-            uint64_t v = 0;
-            for (int u = 0; u < gs; u++)
-                if ((comb >> u) & 1) v ^= sX[gb + u][w];
-            sT[comb][w] = v;
-        }
-        __syncthreads();
-        // one table row per remaining row of the block
-        const int lo = lower ? gb + gs : 0, hi = lower ? nr : gb;
-        for (int e = tid; e < (hi - lo) * TRSM_TW; e += TRSM_THREADS) {
-            int s = lo + e / TRSM_TW, w = e % TRSM_TW;
-            int id = (int)((sL[s] >> gb) & ((1u << gs) - 1));
-            sX[s][w] ^= sT[id][w];
-        }
-        __syncthreads();
-    }
+    if (tid < 64) sInv[lane] = tri_inverse64(sL, lane, lower != 0);
+    build_group_tables(sB, nr, TRSM_K, TRSM_NG, sT, TRSM_TW, tid, TRSM_THREADS);
     for (int e = tid; e < nr * TRSM_TW; e += TRSM_THREADS) {
-        int s = e / TRSM_TW, w = e % TRSM_TW;
-        if (w < tw_n) A[(int64_t)(r0 + s) * stride + w0 + w] = sX[s][w];
+        const int i = e / TRSM_TW, w = e % TRSM_TW;
+        const uint64_t c = sInv[i];
+        uint64_t x = 0;
+#pragma unroll
+        for (int g = 0; g < TRSM_NG; g++)
+            x ^= sT[((g << TRSM_K) + (int)((c >> (TRSM_K * g)) & ((1u << TRSM_K) - 1))) * TRSM_TW + w];
+        if (w < tw_n) A[(int64_t)(r0 + i) * stride + w0 + w] = x;
     }
 }
 
@@ -124,83 +92,114 @@ hipError_t launch_trsm_base(uint64_t *A, int64_t stride, const uint64_t *Lm, int
 }
 
 // ------------------------------------------------------------ table update
+// After a panel with r pivots (rows [R, R + r)), with B the pivot rows' words on
+// the target columns as they were before any update (staged in Bbuf) and L the
+// panel's r x r unit lower triangle:
+//   pivot rows:      U = L^{-1} B                (the triangular solve)
+//   rows below:      x <- x + l U = x + (l L^{-1}) B
+// where l is the row's compressed panel word (its multipliers).  Both are
+// combinations of B rows, so B is tabulated once per block (MakeTable, k rows
+// per table) and every row adds one table row per table (AddRowsFromTable);
+// l L^{-1} comes from tables of 8 rows of L^{-1}.  B is read only from the
+// staging buffer, so blocks never race on the pivot rows they rewrite.
 constexpr int TU_THREADS = 256;
-constexpr int TU_LDS = 64 * 1024;   // table budget per block
+constexpr int TU_LDS = 64 * 1024;   // budget for the B tables of one pass
 
 int table_update_tile_words(int k, int tables) {
     int tw = TU_LDS / (tables * (1 << k) * 8);
-    if (tw > 64) tw = 64;
+    if (tw > 32) tw = 32;
     if (tw < 1) tw = 1;
     return tw;
 }
 
+size_t table_update_lds_bytes(int k, int tables, int TW) {
+    return (size_t)(8 * 256 + 64 + 2 * 64 * TW + tables * (1 << k) * TW) * 8;
+}
+
 __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
     uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk, int b, int w_lo, int w_hi,
-    int k, int tables, int TW) {
-    extern __shared__ uint64_t tu_lds[];   // U rows [64][TW], then tables [tables][1<<k][TW]
+    int k, int tables, int TW, const uint64_t *linv, const uint64_t *Bbuf, int64_t bstride) {
+    extern __shared__ uint64_t tu_lds[];
+    uint64_t *sLT = tu_lds;                 // [8][256]   combinations of L^{-1} rows
+    uint64_t *sInv = sLT + 8 * 256;         // [64]
+    uint64_t *sB = sInv + 64;               // [64][TW]
+    uint64_t *sU = sB + 64 * TW;            // [64][TW]   pivot rows' results
+    uint64_t *sT = sU + 64 * TW;            // [tables][1 << k][TW]
     const int R = rk[b];
     const int R1 = rk[b + 1];
     const int r = R1 - R;
-    if (r <= 0 || R1 >= m) return;
+    if (r <= 0) return;
+    const bool pivots_here = blockIdx.x == 0;
+    if (!pivots_here && R1 >= m) return;
     const int tid = threadIdx.x;
     const int w0 = w_lo + blockIdx.y * TW;
     const int tw_n = min(TW, w_hi - w0);
     if (tw_n <= 0) return;
-    uint64_t *sU = tu_lds;
-    uint64_t *sT = tu_lds + 64 * TW;
-    for (int e = tid; e < r * TW; e += TU_THREADS) {
-        int s = e / TW, w = e % TW;
-        sU[e] = w < tw_n ? A[(int64_t)(R + s) * stride + w0 + w] : 0ull;
+    if (tid < 64) sInv[tid] = linv[tid];
+    for (int e = tid; e < 64 * TW; e += TU_THREADS) {
+        const int t = e / TW, w = e % TW;
+        sB[e] = (t < r && w < tw_n) ? Bbuf[(int64_t)t * bstride + (w0 - w_lo) + w] : 0ull;
+        sU[e] = 0ull;
     }
+    __syncthreads();
+    build_group_tables(sInv, 64, 8, 8, sLT, 1, tid, TU_THREADS);
     const int ng = (r + k - 1) / k;
     const int npass = (ng + tables - 1) / tables;
     const int esz = 1 << k;
+    const uint32_t kmask = (1u << k) - 1;
     const int rows_per_it = TU_THREADS / TW;
     const int my_w = tid % TW, my_row = tid / TW;
     for (int pass = 0; pass < npass; pass++) {
         const int g0 = pass * tables, g1 = min(ng, g0 + tables);
-        __syncthreads();
-        // MakeTable: all combinations of each group's U rows (tile words only)
-        for (int e = tid; e < (g1 - g0) * esz * TW; e += TU_THREADS) {
-            int w = e % TW, comb = (e / TW) % esz, slot = e / (TW * esz);
-            int gb = (g0 + slot) * k, gs = min(k, r - gb);
-            uint64_t v = 0;
-            if (comb < (1 << gs))
-                for (int u = 0; u < gs; u++)
-                    if ((comb >> u) & 1) v ^= sU[(gb + u) * TW + w];
-            sT[e] = v;
+        build_group_tables(sB + (size_t)g0 * k * TW, r - g0 * k, k, g1 - g0, sT, TW, tid,
+                           TU_THREADS);
+        if (pivots_here) {
+            for (int e = tid; e < r * TW; e += TU_THREADS) {
+                const int t = e / TW, w = e % TW;
+                const uint64_t c = sInv[t];
+                uint64_t x = sU[e];
+                for (int g = g0; g < g1; g++)
+                    x ^= sT[((g - g0) * esz + (int)((c >> (k * g)) & kmask)) * TW + w];
+                sU[e] = x;
+            }
         }
-        __syncthreads();
-        // AddRowsFromTable: rows below the pivot rows, one table row per group
         if (my_row < rows_per_it && my_w < tw_n) {
             for (int i = R1 + blockIdx.x * rows_per_it + my_row; i < m;
                  i += gridDim.x * rows_per_it) {
-                const uint64_t lv = A[(int64_t)i * stride + wc];
+                const uint64_t l = A[(int64_t)i * stride + wc];
+                uint64_t c = 0;
+#pragma unroll
+                for (int g8 = 0; g8 < 8; g8++) c ^= sLT[g8 * 256 + (int)((l >> (8 * g8)) & 255)];
                 uint64_t *px = A + (int64_t)i * stride + w0 + my_w;
                 uint64_t x = *px;
-                for (int g = g0; g < g1; g++) {
-                    int gb = g * k, gs = min(k, r - gb);
-                    int id = (int)((lv >> gb) & ((1u << gs) - 1));
-                    x ^= sT[((g - g0) * esz + id) * TW + my_w];
-                }
+                for (int g = g0; g < g1; g++)
+                    x ^= sT[((g - g0) * esz + (int)((c >> (k * g)) & kmask)) * TW + my_w];
                 *px = x;
             }
         }
+        __syncthreads();
     }
+    if (pivots_here)
+        for (int e = tid; e < r * TW; e += TU_THREADS) {
+            const int t = e / TW, w = e % TW;
+            if (w < tw_n) A[(int64_t)(R + t) * stride + w0 + w] = sU[e];
+        }
 }
 
 hipError_t launch_table_update(uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk,
-                               int b, int w_lo, int w_hi, int k, int tables, hipStream_t st) {
+                               int b, int w_lo, int w_hi, int k, int tables, const uint64_t *linv,
+                               const uint64_t *Bbuf, int64_t bstride, int target_blocks,
+                               hipStream_t st) {
     if (w_hi <= w_lo) return hipSuccess;
     int TW = table_update_tile_words(k, tables);
     if (TW > w_hi - w_lo) TW = w_hi - w_lo;
     int ny = (w_hi - w_lo + TW - 1) / TW;
     int rows_per_it = TU_THREADS / TW;
     int nx = (m + rows_per_it - 1) / rows_per_it;
-    int want = (2048 + ny - 1) / ny;   // enough blocks to fill the device
+    int want = (target_blocks + ny - 1) / ny;
     if (nx > want) nx = want;
     if (nx < 1) nx = 1;
-    size_t lds = ((size_t)64 + (size_t)tables * (1 << k)) * TW * 8;
+    size_t lds = table_update_lds_bytes(k, tables, TW);
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void *)table_update_kernel,
@@ -209,7 +208,7 @@ hipError_t launch_table_update(uint64_t *A, int64_t stride, int m, int wc, const
         attr_set = true;
     }
     hipLaunchKernelGGL(table_update_kernel, dim3(nx, ny), dim3(TU_THREADS), lds, st, A, stride, m,
-                       wc, rk, b, w_lo, w_hi, k, tables, TW);
+                       wc, rk, b, w_lo, w_hi, k, tables, TW, linv, Bbuf, bstride);
     return hipGetLastError();
 }
 
@@ -218,36 +217,58 @@ hipError_t launch_table_update(uint64_t *A, int64_t stride, int m, int wc, const
 // columns [c0+n0, c0+n0+r1) move to [c0+r0, c0+r0+r1), row by row as the column
 // swaps "i <-> n0 + (i - r0), from row i" leave them: a row at offset v below
 // the first block's pivots moves min(v + 1, r1) columns and zeroes the vacated ones.
+__device__ inline void shift_row(uint64_t *row, int64_t stride, int c0, int n0, int r0, int r1,
+                                 int v) {
+    const int d = n0 - r0;
+    const int len = min(v + 1, r1);
+    const int D = c0 + r0;             // first destination bit
+    const int S = c0 + n0;             // first source bit
+    const int end = S + len;           // bits [D, end) change
+    for (int w = D >> 6; w <= (end - 1) >> 6; w++) {
+        const int p0 = w * 64;
+        const int sb = p0 + d;         // source of position p0
+        const int sw = sb >> 6, so = sb & 63;
+        const uint64_t lo = sw < stride ? row[sw] : 0ull;
+        const uint64_t hi = (so && sw + 1 < stride) ? row[sw + 1] : 0ull;
+        const uint64_t src = so ? ((lo >> so) | (hi << (64 - so))) : lo;
+        const uint64_t old = row[w];
+        uint64_t mv = 0, clr = 0;
+        int a = max(D, p0), e = min(D + len, p0 + 64);
+        if (e > a) mv = ((e - a) == 64 ? ~0ull : ((1ull << (e - a)) - 1)) << (a - p0);
+        a = max(D + len, p0);
+        e = min(end, p0 + 64);
+        if (e > a) clr = ((e - a) == 64 ? ~0ull : ((1ull << (e - a)) - 1)) << (a - p0);
+        row[w] = (old & ~(mv | clr)) | (src & mv);
+    }
+}
+
 __global__ void compress_shift_kernel(uint64_t *A, int64_t stride, int m, int c0, int n0,
                                       const int32_t *rk, int b0, int b1, int b2) {
     const int R = rk[b0], Rm = rk[b1], Re = rk[b2];
     const int r0 = Rm - R, r1 = Re - Rm;
     if (r0 >= n0 || r1 <= 0) return;
-    const int d = n0 - r0;
-    for (int i = Rm + blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
-        const int v = i - Rm;
-        const int len = min(v + 1, r1);
+    for (int i = Rm + blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
+        shift_row(A + (int64_t)i * stride, stride, c0, n0, r0, r1, i - Rm);
+}
+
+// The shifts of an MMPF block of nwd panels at word wb, innermost first: the
+// block is a right-nested chain of 64-column splits.
+__global__ void compress_chain_kernel(uint64_t *A, int64_t stride, int m, int wb, int nwd,
+                                      const int32_t *rk) {
+    const int Re = rk[wb + nwd];
+    bool any = false;
+    for (int p = 0; p + 1 < nwd; p++) {
+        const int r0 = rk[wb + p + 1] - rk[wb + p];
+        if (r0 < 64 && Re > rk[wb + p + 1]) any = true;
+    }
+    if (!any) return;
+    for (int i = rk[wb + 1] + blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += gridDim.x * blockDim.x) {
         uint64_t *row = A + (int64_t)i * stride;
-        const int D = c0 + r0;             // first destination bit
-        const int S = c0 + n0;             // first source bit
-        const int end = S + len;           // bits [D, end) change
-        for (int w = D >> 6; w <= (end - 1) >> 6; w++) {
-            const int p0 = w * 64;
-            // source bits for positions p0 .. p0+63 are p0 + d ..
-            const int sb = p0 + d;
-            const int sw = sb >> 6, so = sb & 63;
-            uint64_t lo = sw < stride ? row[sw] : 0ull;
-            uint64_t hi = (so && sw + 1 < stride) ? row[sw + 1] : 0ull;
-            uint64_t src = so ? ((lo >> so) | (hi << (64 - so))) : lo;
-            uint64_t old = row[w];
-            // masks over positions p0+j
-            uint64_t mv = 0, clr = 0;
-            int a = max(D, p0), e = min(D + len, p0 + 64);
-            if (e > a) mv = ((e - a) == 64 ? ~0ull : ((1ull << (e - a)) - 1)) << (a - p0);
-            a = max(D + len, p0);
-            e = min(end, p0 + 64);
-            if (e > a) clr = ((e - a) == 64 ? ~0ull : ((1ull << (e - a)) - 1)) << (a - p0);
-            row[w] = (old & ~(mv | clr)) | (src & mv);
+        for (int p = nwd - 2; p >= 0; p--) {
+            const int Rp = rk[wb + p], Rm = rk[wb + p + 1];
+            const int r0 = Rm - Rp, r1 = Re - Rm;
+            if (r0 < 64 && r1 > 0 && i >= Rm) shift_row(row, stride, 64 * (wb + p), 64, r0, r1, i - Rm);
         }
     }
 }
@@ -259,6 +280,17 @@ hipError_t launch_compress_shift(uint64_t *A, int64_t stride, int m, int c0, int
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(compress_shift_kernel, dim3(blocks), dim3(256), 0, st, A, stride, m, c0, n0,
                        rk, b0, b1, b2);
+    return hipGetLastError();
+}
+
+hipError_t launch_compress_chain(uint64_t *A, int64_t stride, int m, int wb, int nwd,
+                                 const int32_t *rk, hipStream_t st) {
+    if (nwd < 2) return hipSuccess;
+    int blocks = (m + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(compress_chain_kernel, dim3(blocks), dim3(256), 0, st, A, stride, m, wb,
+                       nwd, rk);
     return hipGetLastError();
 }
 
