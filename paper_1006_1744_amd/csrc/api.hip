@@ -170,10 +170,10 @@ struct PlsDriver {
     // starting at word lw0 + a / 64; right-hand side words [w_lo, w_hi).
     void trsm_lower(int ib, int ie, int a, int sz, int lw0, int w_lo, int w_hi) {
         if (w_hi <= w_lo || sz <= 0) return;
-        if (sz <= 64) {
+        if (sz <= trsm_block_max_rows()) {
             if (!dry)
-                chk(launch_trsm_base(A, stride, A, stride, m, row_range(ib, ie, a, sz),
-                                     lw0 + a / 64, w_lo, w_hi, rk, 1, st));
+                chk(launch_trsm_block(A, stride, A, stride, m, row_range(ib, ie, a, sz),
+                                      lw0 + a / 64, w_lo, w_hi, rk, 1, (sz + 63) / 64, st));
             return;
         }
         const int h = (sz / 64 / 2) * 64;
@@ -434,9 +434,9 @@ struct UpperSolve {
     // rows [a, min(r, a + sz)) <- U^{-1} rows, solving the last rows first
     void solve(int a, int sz) {
         if (a >= r || sz <= 0) return;
-        if (sz <= 64) {
-            chk(launch_trsm_base(X, sx, U, su, r, row_range(-1, -1, a, sz), a / 64, 0, nwx, rr, 0,
-                                 st));
+        if (sz <= trsm_block_max_rows()) {
+            chk(launch_trsm_block(X, sx, U, su, r, row_range(-1, -1, a, sz), a / 64, 0, nwx, rr, 0,
+                                  (sz + 63) / 64, st));
             return;
         }
         const int h = (sz / 64 / 2) * 64;

@@ -69,6 +69,14 @@ hipError_t launch_trsm_base(uint64_t *A, int64_t stride, const uint64_t *Lm, int
                             RowRange rows, int lw, int w_lo, int w_hi, const int32_t *rk,
                             int lower, hipStream_t st);
 
+// X <- T^{-1} X for up to nbmax (<= trsm_block_max_rows() / 64) blocks of 64 rows
+// `rows` of A; T's rows are the same rows of Lm, the block of 64 columns starting
+// at word lw0 (diagonal block b at word lw0 + b).  lower = 0: unit upper.
+hipError_t launch_trsm_block(uint64_t *A, int64_t stride, const uint64_t *Lm, int64_t sl, int m,
+                             RowRange rows, int lw0, int w_lo, int w_hi, const int32_t *rk,
+                             int lower, int nbmax, hipStream_t st);
+int trsm_block_max_rows();
+
 // Table-driven update after a panel (Section 4.1: MakeTable1 / AddRowsFromTable)
 // on word columns [w_lo, w_hi): the panel's pivot rows become U = L^{-1} B and
 // every row below adds l U, l its compressed panel word; B (the pivot rows as

@@ -38,6 +38,9 @@ struct PanelInfo {
     uint64_t u[64];  // pivot rows' panel words when chosen (reduced by earlier pivots)
     uint64_t linv[64];  // rows of L^{-1} for the panel's r x r unit lower triangle
     int32_t moved[kMovedInts];
+#ifdef GF2_TRACE
+    uint64_t trace[16];
+#endif
 };
 
 __device__ inline int shfl32(int v, int src) { return __shfl(v, src); }
@@ -79,28 +82,13 @@ __device__ inline uint64_t apply_tables(uint64_t x, const int32_t *q, int ta, in
     return x;
 }
 
-// Entry (h, l) of the window, h and l wave-uniform; every register is read
-// with a static index so the window stays in VGPRs.
-__device__ inline uint64_t window_get(const uint64_t (&x)[LEAF_H], int h, int l) {
-    uint64_t v = 0;
-#pragma unroll
-    for (int k = 0; k < LEAF_H; k++) {
-        uint64_t t = readlane64(x[k], l);
-        v = (h == k) ? t : v;
-    }
-    return v;
+// Value v (wave-uniform) written into lane l of a per-lane register.
+__device__ inline uint64_t writelane64(uint64_t old, uint64_t v, int l) {
+    return (int)__lane_id() == l ? v : old;
 }
 
-// Wave-0 bookkeeping of a new pivot t (wave-uniform arguments): the pivot's
-// multipliers in pivot order, Lc = (bit q_s of the pivot word for s < t), give
-// row t of the panel's unit lower triangle L; lane j keeps column j of L^{-1}
-// and extends it by one substitution step.
-__device__ inline void note_pivot(int t, int col, uint64_t pw, int lane, int &lq,
-                                  uint64_t &linvc) {
-    const uint64_t Lc = __ballot(lane < t && ((pw >> lq) & 1ull));
-    if (lane == t) lq = col;
-    const uint64_t bit = (uint64_t)((__popcll(Lc & linvc) & 1) ^ (lane == t ? 1 : 0));
-    linvc |= bit << t;
+__device__ inline int writelane32(int v, int l, int old) {
+    return (int)__lane_id() == l ? v : old;
 }
 
 __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
@@ -112,6 +100,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
     __shared__ uint64_t sT[8][256];   // pending pivots [pa, t), for rows >= F
     __shared__ uint64_t sE[8][256];   // pivots of the last epoch, for rows in [window end, F)
     __shared__ int s_t, s_c, s_F, s_pa, s_brk, s_far, s_tab_lo, s_tab_hi, s_epochs;
+    __shared__ int sOg[LEAF_W];       // first window: original offset of each entry's row
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int R = rk[b];
@@ -119,18 +108,19 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
     const int nc = min(64, n - 64 * wc);
     uint64_t *col = A + (int64_t)R * stride + wc;
     const int NOHIT = 0x7fffffff;
-    // wave 0 state kept across rounds
-    int lq = 0;              // lane s: panel column of pivot s
-    uint64_t linvc = 0;      // lane j: column j of L^{-1}
-    int og[LEAF_H];          // original offset of the row in each window entry
-    bool simple = true;      // one window, no far search: moves read off og[]
+    bool simple = true;      // one window, no far search: moves read off sOg[]
 
+#ifdef GF2_TRACE
+    int ntr = 0;
+#define TR() do { if (tid == 0 && ntr < 14) { info->trace[ntr++] = __builtin_amdgcn_s_memrealtime(); info->trace[ntr++] = __builtin_amdgcn_s_memtime(); } } while (0)
+#else
+#define TR() do {} while (0)
+#endif
+    TR();
     if (tid == 0) {
         s_t = 0; s_c = 0; s_F = 0; s_pa = 0; s_tab_lo = -1; s_tab_hi = -1; s_brk = 0;
         s_far = NOHIT; s_epochs = 0;
     }
-#pragma unroll
-    for (int h = 0; h < LEAF_H; h++) og[h] = lane + 64 * h;
     __syncthreads();
 
     // Invariant at the top of each round: rows at offsets [t, F) are reduced by
@@ -147,74 +137,86 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
         if (need_tab && tid == 0) { s_tab_lo = pa; s_tab_hi = t; }
         const int ts = t;
         if (wave == 0) {
-            uint64_t x[LEAF_H];
-            bool valid[LEAF_H];
-#pragma unroll
-            for (int h = 0; h < LEAF_H; h++) {
-                const int o = ts + lane + 64 * h;
-                valid[h] = o < mrem;
-                uint64_t v = valid[h] ? col[(int64_t)o * stride] : 0;
-                if (valid[h] && o >= F && t > pa) v = apply_tables(v, sQ, pa, t, sT);
-                x[h] = v;
-                og[h] = o;
+            // Window: entries e = lane and 64 + lane hold the rows at offsets ts + e,
+            // all reduced by every pivot found so far.  The search works on the
+            // transpose: lane j holds column j of the window as two 64-bit words
+            // (bit e = entry e), so a column's candidates are one readlane and a
+            // row operation is one masked XOR per lane.
+            const int o0 = ts + lane, o1 = ts + 64 + lane;
+            uint64_t x0 = o0 < mrem ? col[(int64_t)o0 * stride] : 0ull;
+            uint64_t x1 = o1 < mrem ? col[(int64_t)o1 * stride] : 0ull;
+            if (t > pa) {
+                if (o0 < mrem && o0 >= F) x0 = apply_tables(x0, sQ, pa, t, sT);
+                if (o1 < mrem && o1 >= F) x1 = apply_tables(x1, sQ, pa, t, sT);
             }
+            int og0 = o0, og1 = o1;
+            uint64_t m0 = __ballot(o0 < mrem), m1 = __ballot(o1 < mrem);   // candidates
+            TR();
+            uint64_t c0 = transpose64(x0, lane), c1 = transpose64(x1, lane);
+            TR();
+            int fer = -1;   // lane j: window entry of the pivot of column j (this epoch)
             int tt = t, cc = c, brk = 0;
-            while (cc < nc && tt < mrem) {
-                const int es = tt - ts;
-                int fe = -1;
-#pragma unroll
-                for (int h = 0; h < LEAF_H; h++) {
-                    const int e = lane + 64 * h;
-                    const bool cand = valid[h] && e >= es && ((x[h] >> cc) & 1);
-                    const uint64_t bal = __ballot(cand);
-                    if (fe < 0 && bal) fe = 64 * h + __ffsll((unsigned long long)bal) - 1;
-                }
-                if (fe < 0) {
+            while (true) {
+                cc = __builtin_amdgcn_readfirstlane(cc);
+                tt = __builtin_amdgcn_readfirstlane(tt);
+                if (cc >= nc || tt >= mrem) break;
+                const uint64_t b0 = readlane64(c0, cc) & m0;
+                const uint64_t b1 = readlane64(c1, cc) & m1;
+                if ((b0 | b1) == 0) {
                     if (ts + LEAF_W >= mrem) { cc++; continue; }  // zero in every remaining row
                     brk = 1;
                     break;
                 }
-                const int he = fe >> 6, le = fe & 63;
-                const uint64_t pw = window_get(x, he, le);
-                if (fe != es) {
-                    const int hs = es >> 6, ls = es & 63;
-                    const uint64_t sw = window_get(x, hs, ls);
-                    int og_e = 0, og_s = 0;
-#pragma unroll
-                    for (int h = 0; h < LEAF_H; h++) {
-                        const int ve = __builtin_amdgcn_readlane(og[h], le);
-                        const int vs = __builtin_amdgcn_readlane(og[h], ls);
-                        og_e = (h == he) ? ve : og_e;
-                        og_s = (h == hs) ? vs : og_s;
-                    }
-#pragma unroll
-                    for (int h = 0; h < LEAF_H; h++) {
-                        if (h == hs && lane == ls) { x[h] = pw; og[h] = og_e; }
-                        if (h == he && lane == le) { x[h] = sw; og[h] = og_s; }
-                    }
-                }
-                if (lane == 0) {
-                    sU[tt] = pw;
-                    sQ[tt] = cc;
-                    sPrel[tt] = ts + fe;
-                    P[R + tt] = R + ts + fe;
-                    Q[R + tt] = 64 * wc + cc;
-                }
-                note_pivot(tt, cc, pw, lane, lq, linvc);
-                const uint64_t above = cc == 63 ? 0ull : (~0ull << (cc + 1));
-                const uint64_t add = pw & above;
-#pragma unroll
-                for (int h = 0; h < LEAF_H; h++) {
-                    const int e = lane + 64 * h;
-                    if (valid[h] && e > es && ((x[h] >> cc) & 1)) x[h] ^= add;
-                }
+                // first candidate with a one: entry fe = fl (+ 64 if in the second half)
+                const bool in1 = b0 == 0;
+                const uint64_t bb = in1 ? b1 : b0;
+                const int fl = __ffsll((unsigned long long)bb) - 1;
+                const int fe = fl + (in1 ? 64 : 0);
+                const int es = tt - ts;   // < 64: pivots fill the window from its start
+                const uint64_t fbit = 1ull << fl;
+                // rows with a one in column cc other than the pivot add the pivot row on
+                // the columns right of cc: column j > cc flips them where the pivot has a one
+                const uint64_t E0 = in1 ? b0 : (b0 & ~fbit);
+                const uint64_t E1 = in1 ? (b1 & ~fbit) : b1;
+                const uint64_t src = in1 ? c1 : c0;
+                const bool flip = lane > cc && ((src >> fl) & 1ull);
+                c0 ^= flip ? E0 : 0ull;
+                c1 ^= flip ? E1 : 0ull;
+                // transposition of entries es and fe (no-op when equal)
+                const uint64_t src2 = in1 ? c1 : c0;
+                const uint64_t d = ((c0 >> es) ^ (src2 >> fl)) & 1ull;
+                c0 ^= (d << es) ^ (in1 ? 0ull : (d << fl));
+                c1 ^= in1 ? (d << fl) : 0ull;
+                const int ogs = __builtin_amdgcn_readlane(og0, es);
+                const int oge = in1 ? __builtin_amdgcn_readlane(og1, fl)
+                                    : __builtin_amdgcn_readlane(og0, fl);
+                og0 = lane == es ? oge : og0;
+                og0 = (!in1 && lane == fl) ? ogs : og0;
+                og1 = (in1 && lane == fl) ? ogs : og1;
+                fer = lane == cc ? fe : fer;
+                m0 &= ~(1ull << es);
                 tt++;
                 cc++;
             }
-#pragma unroll
-            for (int h = 0; h < LEAF_H; h++) {
-                const int o = ts + lane + 64 * h;
-                if (valid[h]) col[(int64_t)o * stride] = x[h];
+            TR();
+            x0 = transpose64(c0, lane);
+            x1 = transpose64(c1, lane);
+            if (o0 < mrem) col[(int64_t)o0 * stride] = x0;
+            if (o1 < mrem) col[(int64_t)o1 * stride] = x1;
+            TR();
+            // bookkeeping of the pivots [t, tt), one lane per column
+            const uint64_t isp = __ballot(fer >= 0);
+            if (fer >= 0) {
+                const int pidx = t + __popcll(isp & ((1ull << lane) - 1));
+                P[R + pidx] = R + ts + fer;
+                Q[R + pidx] = 64 * wc + lane;
+                sQ[pidx] = lane;
+                sPrel[pidx] = ts + fer;
+            }
+            if (lane < tt - t) sU[t + lane] = x0;   // pivot rows stay where they were put
+            if (epochs == 0) {
+                sOg[lane] = og0;
+                sOg[64 + lane] = og1;
             }
             if (lane == 0) {
                 s_t = tt;
@@ -287,7 +289,6 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
             Q[R + t1] = 64 * wc + c1;
         }
         __syncthreads();
-        if (wave == 0) note_pivot(t1, c1, sU[t1], lane, lq, linvc);
         {
             // rows after f up to the new frontier may hold a one in column c1
             const uint64_t pw = sU[t1];
@@ -309,19 +310,21 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
     }
     __syncthreads();
 
+    TR();
     const int r = max(0, min(s_t, mrem));
     if (wave == 0) {
         int32_t *mv = info->moved;
         if (simple) {
-            // one window starting at offset 0: entry e holds the row from og[e]
+            // one window starting at offset 0: entry e holds the row from sOg[e]
             int base_cnt = 0;
 #pragma unroll
             for (int h = 0; h < LEAF_H; h++) {
                 const int e = lane + 64 * h;
-                const bool mvd = og[h] != e && e < mrem;
+                const int og = sOg[e];
+                const bool mvd = og != e && e < mrem;
                 const uint64_t bal = __ballot(mvd);
                 const int idx = base_cnt + __popcll(bal & ((1ull << lane) - 1));
-                if (mvd) { mv[1 + 2 * idx] = e; mv[2 + 2 * idx] = og[h]; }
+                if (mvd) { mv[1 + 2 * idx] = e; mv[2 + 2 * idx] = og; }
                 base_cnt += __popcll(bal);
             }
             if (lane == 0) mv[0] = base_cnt;
@@ -360,11 +363,20 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
             if (lane < nk) { mv[1 + 2 * lane] = pos0; mv[2 + 2 * lane] = src0; }
             if (lane + 64 < nk) { mv[1 + 2 * (lane + 64)] = pos1; mv[2 + 2 * (lane + 64)] = src1; }
         }
-        // L^{-1}: identity past r, then columns -> rows
-        if (lane >= r) linvc = 1ull << lane;
-        info->linv[lane] = transpose64(linvc, lane);
+        TR();
+        // L (r x r, pivot order): L[t][s] is bit q[s] of the pivot word sU[t].
+        // Lane j solves L x = e_j column by column (x ^= L[:, s] where x[s] = 1),
+        // then the columns of L^{-1} are transposed into rows.  Identity past r.
+        const uint64_t urow = lane < r ? sU[lane] : 0ull;
+        uint64_t xcol = 1ull << lane;
+        for (int s2 = 0; s2 + 1 < r; s2++) {
+            const int qs = sQ[s2];
+            const uint64_t Lcol = __ballot(lane > s2 && lane < r && ((urow >> qs) & 1ull));
+            if ((xcol >> s2) & 1ull) xcol ^= Lcol;
+        }
+        info->linv[lane] = transpose64(xcol, lane);
         info->q[lane] = lane < r ? sQ[lane] : lane;
-        info->u[lane] = lane < r ? sU[lane] : 0ull;
+        info->u[lane] = urow;
     }
     if (tid == 0) {
         int cmp = 0;
@@ -375,6 +387,10 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
         info->compress = cmp;
         rk[b + 1] = R + r;
     }
+    TR();
+#ifdef GF2_TRACE
+    if (tid == 0) info->trace[15] = ntr;
+#endif
 }
 
 // Final pass over the panel (blocks [0, nfin)) and the other word columns of

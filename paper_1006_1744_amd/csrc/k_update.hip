@@ -91,6 +91,106 @@ hipError_t launch_trsm_base(uint64_t *A, int64_t stride, const uint64_t *Lm, int
     return hipGetLastError();
 }
 
+// ------------------------------------------------------- blocked TRSM
+// X <- T^{-1} X for up to TB_NB blocks of 64 rows in one launch (unit lower or
+// unit upper T, its rows in Lm).  Each block's own 64 x 64 inverse is formed by
+// one wave; the blocks are then solved in order (forward for lower, backward
+// for upper): a block first adds, for every block already solved, one table row
+// per group of 4 multipliers (AddRowsFromTable on the tables of that block's
+// solution, MakeTable with k = 4), then is multiplied by its diagonal inverse
+// with the same kind of tables.  One launch replaces the bottom levels of the
+// recursive solve (Section 5 reduces it to products), whose products would be
+// too small to fill the device.
+constexpr int TB_THREADS = 256;
+constexpr int TB_NB = 16;
+constexpr int TB_TW = 2;
+
+__global__ __launch_bounds__(TB_THREADS) void trsm_block_kernel(
+    uint64_t *A, int64_t stride, const uint64_t *Lm, int64_t sl, int m, RowRange rows, int lw0,
+    int w_lo, int w_hi, const int32_t *rk, int lower, int nbmax) {
+    __shared__ uint64_t sX[TB_NB * 64 * TB_TW];
+    __shared__ uint64_t sT[TB_NB * 256 * TB_TW];
+    __shared__ uint64_t sC[256 * TB_TW];
+    __shared__ uint64_t sInv[TB_NB * 64];
+    __shared__ uint64_t sDiag[TB_THREADS / 64][64];
+    int r0, r1;
+    eval_range(rk, m, rows, r0, r1);
+    const int nr = min(r1 - r0, nbmax * 64);
+    if (nr <= 1) return;
+    const int nb = (nr + 63) / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int w0 = w_lo + blockIdx.x * TB_TW;
+    const int tw_n = min(TB_TW, w_hi - w0);
+    if (tw_n <= 0) return;
+    for (int e = tid; e < nb * 64 * TB_TW; e += TB_THREADS) {
+        const int r = e / TB_TW, w = e % TB_TW;
+        sX[e] = (r < nr && w < tw_n) ? A[(int64_t)(r0 + r) * stride + w0 + w] : 0ull;
+    }
+    for (int b = wave; b < nb; b += TB_THREADS / 64) {
+        const int row = 64 * b + lane;
+        const int valid = nr - 64 * b;
+        const uint64_t keep = valid >= 64 ? ~0ull : ((1ull << valid) - 1);
+        sDiag[wave][lane] = row < nr ? (Lm[(int64_t)(r0 + row) * sl + lw0 + b] & keep) : 0ull;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        sInv[64 * b + lane] = tri_inverse64(sDiag[wave], lane, lower != 0);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    for (int bi = 0; bi < nb; bi++) {
+        const int b = lower ? bi : nb - 1 - bi;
+        const int bn = min(64, nr - 64 * b);
+        if (bi > 0) {
+            const int a_lo = lower ? 0 : b + 1, a_hi = lower ? b : nb;
+            for (int e = tid; e < bn * TB_TW; e += TB_THREADS) {
+                const int i = e / TB_TW, w = e % TB_TW;
+                const int row = 64 * b + i;
+                uint64_t x = sX[row * TB_TW + w];
+                const uint64_t *lrow = Lm + (int64_t)(r0 + row) * sl + lw0;
+                for (int a = a_lo; a < a_hi; a++) {
+                    const uint64_t lv = lrow[a];
+                    const uint64_t *T = sT + (size_t)a * 256 * TB_TW;
+#pragma unroll
+                    for (int g = 0; g < 16; g++)
+                        x ^= T[((g << 4) + (int)((lv >> (4 * g)) & 15)) * TB_TW + w];
+                }
+                sX[row * TB_TW + w] = x;
+            }
+            __syncthreads();
+        }
+        build_group_tables(sX + (size_t)64 * b * TB_TW, bn, 4, 16, sC, TB_TW, tid, TB_THREADS);
+        for (int e = tid; e < bn * TB_TW; e += TB_THREADS) {
+            const int i = e / TB_TW, w = e % TB_TW;
+            const uint64_t c = sInv[64 * b + i];
+            uint64_t x = 0;
+#pragma unroll
+            for (int g = 0; g < 16; g++) x ^= sC[((g << 4) + (int)((c >> (4 * g)) & 15)) * TB_TW + w];
+            sX[(64 * b + i) * TB_TW + w] = x;
+        }
+        __syncthreads();
+        if (bi + 1 < nb)
+            build_group_tables(sX + (size_t)64 * b * TB_TW, bn, 4, 16, sT + (size_t)b * 256 * TB_TW,
+                               TB_TW, tid, TB_THREADS);
+    }
+    for (int e = tid; e < nr * TB_TW; e += TB_THREADS) {
+        const int r = e / TB_TW, w = e % TB_TW;
+        if (w < tw_n) A[(int64_t)(r0 + r) * stride + w0 + w] = sX[e];
+    }
+}
+
+int trsm_block_max_rows() { return TB_NB * 64; }
+
+hipError_t launch_trsm_block(uint64_t *A, int64_t stride, const uint64_t *Lm, int64_t sl, int m,
+                             RowRange rows, int lw0, int w_lo, int w_hi, const int32_t *rk,
+                             int lower, int nbmax, hipStream_t st) {
+    if (w_hi <= w_lo) return hipSuccess;
+    if (nbmax > TB_NB) nbmax = TB_NB;
+    int nb = (w_hi - w_lo + TB_TW - 1) / TB_TW;
+    hipLaunchKernelGGL(trsm_block_kernel, dim3(nb), dim3(TB_THREADS), 0, st, A, stride, Lm, sl, m,
+                       rows, lw0, w_lo, w_hi, rk, lower, nbmax);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ table update
 // After a panel with r pivots (rows [R, R + r)), with B the pivot rows' words on
 // the target columns as they were before any update (staged in Bbuf) and L the

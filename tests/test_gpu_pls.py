@@ -143,12 +143,16 @@ def test_pls_4096(seed):
 # ---------------------------------------------------------------- RREF
 @pytest.mark.parametrize("m,n,kind", [(64, 64, "half"), (300, 257, "half"), (257, 300, "half"),
                                       (500, 700, "planted"), (700, 500, "sparse"),
-                                      (1, 50, "half"), (50, 1, "half"), (200, 200, "zero")])
+                                      (1, 50, "half"), (50, 1, "half"), (200, 200, "zero"),
+                                      (600, 3000, "half"), (1500, 1400, "planted1200"),
+                                      (1300, 4000, "half")])
 def test_rref(m, n, kind):
     if kind == "half":
         A = synth.random_half(m, n, m + 2 * n)
     elif kind == "planted":
         A = synth.planted(m, n, 333, 9, p=0.5)
+    elif kind == "planted1200":
+        A = synth.planted(m, n, 1200, 9, p=0.5)
     elif kind == "sparse":
         A = synth.random_bernoulli(m, n, 0.01, 4)
     else:
