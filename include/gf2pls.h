@@ -146,8 +146,16 @@ typedef struct gf2_prof_stats {
     double total_ops;
 } gf2_prof_stats;
 
+typedef struct gf2_prof_launch {
+    double ms;
+    int64_t m, n, k;
+} gf2_prof_launch;
+
 int gf2_prof_enable(gf2_ctx *ctx, int32_t *dev_log, int64_t log_slots);
 int gf2_prof_read(gf2_ctx *ctx, gf2_prof_stats *out);
+/* The recorded launches one by one (up to max, in launch order) without clearing
+ * them; *count receives the number written.  Call before gf2_prof_read. */
+int gf2_prof_read_launches(gf2_ctx *ctx, gf2_prof_launch *out, int64_t max, int64_t *count);
 
 #ifdef __cplusplus
 }

@@ -49,6 +49,11 @@ class ProfStats(ctypes.Structure):
                 ("total_ops", ctypes.c_double)]
 
 
+class ProfLaunch(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("k", ctypes.c_int64)]
+
+
 def _load():
     if not os.path.exists(_LIB_PATH):
         raise ImportError(f"{_LIB_PATH} is not built; run python -m paper_1006_1744_amd.build")
@@ -80,6 +85,9 @@ def _load():
     L.gf2_prof_enable.restype = i32
     L.gf2_prof_read.argtypes = [vp, ctypes.POINTER(ProfStats)]
     L.gf2_prof_read.restype = i32
+    L.gf2_prof_read_launches.argtypes = [vp, ctypes.POINTER(ProfLaunch), i64,
+                                         ctypes.POINTER(ctypes.c_int64)]
+    L.gf2_prof_read_launches.restype = i32
     return L
 
 
@@ -231,3 +239,12 @@ def prof_read(device=None) -> dict:
     st = ProfStats()
     _check(get_lib().gf2_prof_read(ctx(dev), ctypes.byref(st)))
     return {"launches": int(st.launches), "ms": float(st.total_ms), "ops": float(st.total_ops)}
+
+
+def prof_launches(max_count: int = 1 << 16, device=None) -> list[tuple]:
+    """(ms, M, N, K) of each recorded product launch, in launch order."""
+    dev = torch.cuda.current_device() if device is None else device
+    arr = (ProfLaunch * max_count)()
+    cnt = ctypes.c_int64()
+    _check(get_lib().gf2_prof_read_launches(ctx(dev), arr, max_count, ctypes.byref(cnt)))
+    return [(arr[i].ms, arr[i].m, arr[i].n, arr[i].k) for i in range(cnt.value)]

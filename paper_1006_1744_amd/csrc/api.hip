@@ -298,6 +298,31 @@ int gf2_prof_enable(gf2_ctx *ctx, int32_t *dev_log, int64_t log_slots) {
     return GF2_OK;
 }
 
+int gf2_prof_read_launches(gf2_ctx *ctx, gf2_prof_launch *out, int64_t max, int64_t *count) {
+    if (!ctx || !count || (max > 0 && !out)) return GF2_E_ARG;
+    *count = 0;
+    if (ctx->recs.empty()) return GF2_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return GF2_E_HIP;
+    if (hipEventSynchronize(ctx->recs.back().b) != hipSuccess) return GF2_E_HIP;
+    std::vector<int32_t> log(2 * ctx->recs.size());
+    if (hipMemcpy(log.data(), ctx->plog, log.size() * sizeof(int32_t), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return GF2_E_HIP;
+    int64_t k = 0;
+    for (const ProfRec &r : ctx->recs) {
+        if (k >= max) break;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return GF2_E_HIP;
+        out[k].ms = ms;
+        out[k].m = log[2 * r.slot];
+        out[k].n = r.ncols;
+        out[k].k = log[2 * r.slot + 1];
+        k++;
+    }
+    *count = k;
+    return GF2_OK;
+}
+
 int gf2_prof_read(gf2_ctx *ctx, gf2_prof_stats *out) {
     if (!ctx || !out) return GF2_E_ARG;
     out->launches = 0;
