@@ -196,7 +196,7 @@ struct PlsDriver {
                                 bstride, wc + 1, wb + nwd, st));
             if (upd && !dry)
                 chk(launch_table_update(A, stride, m, wc, rk, wc, wc + 1, wb + nwd, s.k, s.tables,
-                                        linv, Bbuf, bstride, 2 * cus, st));
+                                        linv, Bbuf, bstride, cus, st));
         }
         if (!dry) chk(launch_compress_chain(A, stride, m, wb, nwd, rk, st));
     }

@@ -67,20 +67,27 @@ __device__ inline uint64_t tri_inverse64(const uint64_t *rows, int lane, bool lo
 // T[(g * 2^k + e) * TW + w] = XOR of rows g*k + u with bit u of e set (rows
 // past nrows read as zero), word w of a TW-word tile.  Built by doubling, one
 // level per barrier: entries [2^l, 2^(l+1)) = entries [0, 2^l) + row g*k + l.
-// rows: LDS [>= ng*k][TW].  All threads of the block must call it.
+// Thread tid works on word tid % TW of entries tid / TW, tid / TW + nthr / TW,
+// ... (one division per call, shifts inside).  rows: LDS [>= ng*k][TW];
+// TW <= nthr.  All threads of the block must call it.
 __device__ inline void build_group_tables(const uint64_t *rows, int nrows, int k, int ng,
                                           uint64_t *T, int TW, int tid, int nthr) {
     const int esz = 1 << k;
-    for (int e = tid; e < ng * TW; e += nthr) T[(e / TW) * esz * TW + (e % TW)] = 0ull;
+    const int wq = tid % TW, pq = tid / TW, pstep = nthr / TW;
+    const bool on = pq < pstep;
+    if (on)
+        for (int g = pq; g < ng; g += pstep) T[(size_t)g * esz * TW + wq] = 0ull;
     __syncthreads();
     for (int l = 0; l < k; l++) {
         const int half = 1 << l;
-        for (int e = tid; e < ng * half * TW; e += nthr) {
-            const int w = e % TW, idx = (e / TW) % half, g = e / (TW * half);
-            const int row = g * k + l;
-            const uint64_t add = row < nrows ? rows[row * TW + w] : 0ull;
-            T[((size_t)g * esz + half + idx) * TW + w] = T[((size_t)g * esz + idx) * TW + w] ^ add;
-        }
+        if (on)
+            for (int p = pq; p < (ng << l); p += pstep) {
+                const int g = p >> l, idx = p & (half - 1);
+                const int row = g * k + l;
+                const uint64_t add = row < nrows ? rows[row * TW + wq] : 0ull;
+                const size_t t0 = ((size_t)g * esz + idx) * TW + wq;
+                T[t0 + (size_t)half * TW] = T[t0] ^ add;
+            }
         __syncthreads();
     }
 }

@@ -395,8 +395,16 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
 
 // Final pass over the panel (blocks [0, nfin)) and the other word columns of
 // the moved rows (blocks [nfin, ...)), which touch disjoint words.
+//  * final pass: rows >= F receive the pending pivots [pa, r) through their
+//    tables, and every row gets the panel's "compress L" column swaps; each
+//    thread holds POST_ROWS rows so that their loads are in flight together.
+//  * moves: the (destination, source) list goes to LDS once; a block copies
+//    SWAP_W word columns of every moved row through LDS (all reads, one
+//    barrier, all writes), and stages the pivot rows' words on [bw_lo, bw_hi)
+//    for the table update that follows from the same copies.
 constexpr int POST_THREADS = 256;
-constexpr int SWAP_COLS = 64;
+constexpr int POST_ROWS = 4;
+constexpr int SWAP_W = 16;
 
 __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
     uint64_t *A, int64_t stride, int m, int wc, int nwords, const int32_t *rk, int b,
@@ -404,63 +412,85 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
     __shared__ uint64_t sT[8][256];
     __shared__ uint64_t sU[64];
     __shared__ int32_t sQ[64];
-    __shared__ uint64_t stage[kMaxMoved][SWAP_COLS];
+    __shared__ uint64_t stage[kMaxMoved * SWAP_W];
+    __shared__ int32_t sDst[kMaxMoved], sSrc[kMaxMoved];
+    __shared__ int32_t sPk[64];
     const int tid = threadIdx.x;
     const int R = rk[b];
     const int mrem = m - R;
     if (mrem <= 0) return;
     const int r = info->r, F = info->F, pa = info->pa, cmp = info->compress;
     if ((int)blockIdx.x < nfin) {
+        const bool pend = (F < mrem) && (r > pa);
+        if (!pend && !cmp) return;
         if (tid < 64) {
             sU[tid] = info->u[tid];
             sQ[tid] = info->q[tid];
         }
         __syncthreads();
-        const bool pend = (F < mrem) && (r > pa);
         if (pend) build_tables(sU, sQ, pa, r, sT, tid, POST_THREADS);
         __syncthreads();
-        if (!pend && !cmp) return;
         uint64_t *col = A + (int64_t)R * stride + wc;
-        for (int o = blockIdx.x * POST_THREADS + tid; o < mrem; o += nfin * POST_THREADS) {
-            uint64_t v = col[(int64_t)o * stride];
-            uint64_t w = v;
-            if (pend && o >= F) w = apply_tables(w, sQ, pa, r, sT);
-            if (cmp) {
-                // compress L: swap panel columns s and q[s] in rows o >= s
-                int lim = min(o + 1, r);
-                for (int s = 0; s < lim; s++) {
-                    int qs = sQ[s];
-                    if (qs != s) {
-                        uint64_t d = ((w >> s) ^ (w >> qs)) & 1ull;
-                        w ^= (d << s) | (d << qs);
+        const int step = nfin * POST_THREADS * POST_ROWS;
+        for (int base = blockIdx.x * POST_THREADS * POST_ROWS; base < mrem; base += step) {
+            uint64_t v[POST_ROWS];
+#pragma unroll
+            for (int u = 0; u < POST_ROWS; u++) {
+                const int o = base + u * POST_THREADS + tid;
+                v[u] = o < mrem ? col[(int64_t)o * stride] : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < POST_ROWS; u++) {
+                const int o = base + u * POST_THREADS + tid;
+                if (o >= mrem) continue;
+                uint64_t w = v[u];
+                if (pend && o >= F) w = apply_tables(w, sQ, pa, r, sT);
+                if (cmp) {
+                    // compress L: swap panel columns s and q[s] in rows o >= s
+                    const int lim = min(o + 1, r);
+                    for (int s2 = 0; s2 < lim; s2++) {
+                        const int qs = sQ[s2];
+                        if (qs != s2) {
+                            const uint64_t d = ((w >> s2) ^ (w >> qs)) & 1ull;
+                            w ^= (d << s2) | (d << qs);
+                        }
                     }
                 }
+                if (w != v[u]) col[(int64_t)o * stride] = w;
             }
-            if (w != v) col[(int64_t)o * stride] = w;
         }
         return;
     }
-    // moved rows, other word columns: stage every source, then write
     const int32_t *mv = info->moved;
     const int nk = mv[0];
-    const int w = (blockIdx.x - nfin) * SWAP_COLS + (tid & (SWAP_COLS - 1));
-    const int part = tid / SWAP_COLS;          // POST_THREADS / SWAP_COLS parts
-    const bool act = w < nwords && w != wc;
-    if (nk > 0) {
-        for (int k = part; k < nk; k += POST_THREADS / SWAP_COLS)
-            stage[k][tid & (SWAP_COLS - 1)] =
-                act ? A[(int64_t)(R + mv[2 + 2 * k]) * stride + w] : 0;
-        __syncthreads();
-        if (act)
-            for (int k = part; k < nk; k += POST_THREADS / SWAP_COLS)
-                A[(int64_t)(R + mv[1 + 2 * k]) * stride + w] = stage[k][tid & (SWAP_COLS - 1)];
+    const int w0 = ((int)blockIdx.x - nfin) * SWAP_W;
+    if (tid < nk) {
+        sDst[tid] = mv[1 + 2 * tid];
+        sSrc[tid] = mv[2 + 2 * tid];
     }
-    // the pivot rows' words on [bw_lo, bw_hi), for the update that follows
-    if (Bbuf != nullptr && bw_hi > bw_lo) {
-        __syncthreads();
-        if (w >= bw_lo && w < bw_hi)
-            for (int t = part; t < r; t += POST_THREADS / SWAP_COLS)
-                Bbuf[(int64_t)t * bstride + (w - bw_lo)] = A[(int64_t)(R + t) * stride + w];
+    if (tid < 64) sPk[tid] = -1;
+    __syncthreads();
+    if (tid < nk && sDst[tid] < 64) sPk[sDst[tid]] = tid;
+    for (int e = tid; e < nk * SWAP_W; e += POST_THREADS) {
+        const int k = e / SWAP_W, w = w0 + e % SWAP_W;
+        if (w < nwords && w != wc) stage[e] = A[(int64_t)(R + sSrc[k]) * stride + w];
+    }
+    __syncthreads();
+    for (int e = tid; e < nk * SWAP_W; e += POST_THREADS) {
+        const int k = e / SWAP_W, w = w0 + e % SWAP_W;
+        if (w < nwords && w != wc) A[(int64_t)(R + sDst[k]) * stride + w] = stage[e];
+    }
+    // the pivot rows' words on [bw_lo, bw_hi) after the moves: a moved pivot row
+    // takes the staged copy, any other is not written by this launch
+    const int blo = max(bw_lo, w0), bhi = min(bw_hi, min(w0 + SWAP_W, nwords));
+    if (Bbuf != nullptr && bhi > blo) {
+        const int bw = bhi - blo;
+        for (int e = tid; e < r * bw; e += POST_THREADS) {
+            const int t = e / bw, w = blo + e % bw;
+            const int k = sPk[t];
+            Bbuf[(int64_t)t * bstride + (w - bw_lo)] =
+                k >= 0 ? stage[k * SWAP_W + (w - w0)] : A[(int64_t)(R + t) * stride + w];
+        }
     }
 }
 
@@ -473,10 +503,10 @@ hipError_t launch_leaf(uint64_t *A, int64_t stride, int m, int n, int wc, int32_
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int nwords = (n + 63) / 64;
-    int nfin = (m + POST_THREADS - 1) / POST_THREADS;
-    if (nfin > 512) nfin = 512;
+    int nfin = (m + POST_THREADS * POST_ROWS - 1) / (POST_THREADS * POST_ROWS);
+    if (nfin > 256) nfin = 256;
     if (nfin < 1) nfin = 1;
-    int nswap = (nwords + SWAP_COLS - 1) / SWAP_COLS;
+    int nswap = (nwords + SWAP_W - 1) / SWAP_W;
     hipLaunchKernelGGL(panel_post_kernel, dim3(nfin + nswap), dim3(POST_THREADS), 0, st, A,
                        stride, m, wc, nwords, rk, b, info, nfin, Bbuf, bstride, bw_lo, bw_hi);
     return hipGetLastError();

@@ -16,6 +16,8 @@
 //                    pass over the rows.
 // compress_shift_kernel  final "compress L" of Section 5.
 // finalize_kernel    P, Q tails and the rank.
+#include <algorithm>
+
 #include "gf2_device.h"
 #include "gf2_internal.h"
 
@@ -112,7 +114,8 @@ __global__ __launch_bounds__(TB_THREADS) void trsm_block_kernel(
     __shared__ uint64_t sT[TB_NB * 256 * TB_TW];
     __shared__ uint64_t sC[256 * TB_TW];
     __shared__ uint64_t sInv[TB_NB * 64];
-    __shared__ uint64_t sDiag[TB_THREADS / 64][64];
+    __shared__ uint64_t sDiag[TB_NB * 64];
+    __shared__ uint64_t sL[64 * TB_NB];      // L words of the current block's rows
     int r0, r1;
     eval_range(rk, m, rows, r0, r1);
     const int nr = min(r1 - r0, nbmax * 64);
@@ -126,29 +129,44 @@ __global__ __launch_bounds__(TB_THREADS) void trsm_block_kernel(
         const int r = e / TB_TW, w = e % TB_TW;
         sX[e] = (r < nr && w < tw_n) ? A[(int64_t)(r0 + r) * stride + w0 + w] : 0ull;
     }
-    for (int b = wave; b < nb; b += TB_THREADS / 64) {
-        const int row = 64 * b + lane;
+    // every diagonal block's rows at once, then one wave per block inverts
+    for (int e = tid; e < nb * 64; e += TB_THREADS) {
+        const int b = e >> 6, row = e;
         const int valid = nr - 64 * b;
         const uint64_t keep = valid >= 64 ? ~0ull : ((1ull << valid) - 1);
-        sDiag[wave][lane] = row < nr ? (Lm[(int64_t)(r0 + row) * sl + lw0 + b] & keep) : 0ull;
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        sInv[64 * b + lane] = tri_inverse64(sDiag[wave], lane, lower != 0);
-        __builtin_amdgcn_wave_barrier();
+        sDiag[e] = row < nr ? (Lm[(int64_t)(r0 + row) * sl + lw0 + b] & keep) : 0ull;
     }
+    // L words (all TB_NB word columns) of one block's rows, TB_LPT per thread
+    constexpr int TB_LPT = 64 * TB_NB / TB_THREADS;
+    uint64_t pre[TB_LPT];
+    auto load_l = [&](int b) {
+#pragma unroll
+        for (int j = 0; j < TB_LPT; j++) {
+            const int e = tid + TB_THREADS * j;
+            const int row = 64 * b + e / TB_NB, a = e % TB_NB;
+            pre[j] = (row < nr && a < nb && a != b) ? Lm[(int64_t)(r0 + row) * sl + lw0 + a] : 0ull;
+        }
+    };
+    load_l(lower ? 0 : nb - 1);
+    __syncthreads();
+    for (int b = wave; b < nb; b += TB_THREADS / 64)
+        sInv[64 * b + lane] = tri_inverse64(sDiag + 64 * b, lane, lower != 0);
     __syncthreads();
     for (int bi = 0; bi < nb; bi++) {
         const int b = lower ? bi : nb - 1 - bi;
         const int bn = min(64, nr - 64 * b);
+#pragma unroll
+        for (int j = 0; j < TB_LPT; j++) sL[tid + TB_THREADS * j] = pre[j];
+        __syncthreads();
+        if (bi + 1 < nb) load_l(lower ? b + 1 : b - 1);   // in flight during this block
         if (bi > 0) {
             const int a_lo = lower ? 0 : b + 1, a_hi = lower ? b : nb;
             for (int e = tid; e < bn * TB_TW; e += TB_THREADS) {
                 const int i = e / TB_TW, w = e % TB_TW;
                 const int row = 64 * b + i;
                 uint64_t x = sX[row * TB_TW + w];
-                const uint64_t *lrow = Lm + (int64_t)(r0 + row) * sl + lw0;
                 for (int a = a_lo; a < a_hi; a++) {
-                    const uint64_t lv = lrow[a];
+                    const uint64_t lv = sL[i * TB_NB + a];
                     const uint64_t *T = sT + (size_t)a * 256 * TB_TW;
 #pragma unroll
                     for (int g = 0; g < 16; g++)
@@ -202,12 +220,18 @@ hipError_t launch_trsm_block(uint64_t *A, int64_t stride, const uint64_t *Lm, in
 // per table) and every row adds one table row per table (AddRowsFromTable);
 // l L^{-1} comes from tables of 8 rows of L^{-1}.  B is read only from the
 // staging buffer, so blocks never race on the pivot rows they rewrite.
+// One thread owns one row and all TW (<= TU_TWMAX) words of the block's tile,
+// so l L^{-1} is formed once per row and the row's loads are issued together;
+// the grid is sized to be resident in one round.
 constexpr int TU_THREADS = 256;
-constexpr int TU_LDS = 64 * 1024;   // budget for the B tables of one pass
+constexpr int TU_TWMAX = 8;
+constexpr int TU_TABLE_LDS = 120 * 1024;   // budget for the B tables of one pass
+constexpr int TU_LDS_MAX = 150 * 1024;
+constexpr int CU_LDS = 160 * 1024;
 
 int table_update_tile_words(int k, int tables) {
-    int tw = TU_LDS / (tables * (1 << k) * 8);
-    if (tw > 32) tw = 32;
+    int tw = TU_TABLE_LDS / (tables * (1 << k) * 8);
+    if (tw > TU_TWMAX) tw = TU_TWMAX;
     if (tw < 1) tw = 1;
     return tw;
 }
@@ -235,55 +259,70 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
     const int w0 = w_lo + blockIdx.y * TW;
     const int tw_n = min(TW, w_hi - w0);
     if (tw_n <= 0) return;
+    const int wq = tid % TW, pq = tid / TW, pstep = TU_THREADS / TW;
     if (tid < 64) sInv[tid] = linv[tid];
-    for (int e = tid; e < 64 * TW; e += TU_THREADS) {
-        const int t = e / TW, w = e % TW;
-        sB[e] = (t < r && w < tw_n) ? Bbuf[(int64_t)t * bstride + (w0 - w_lo) + w] : 0ull;
-        sU[e] = 0ull;
-    }
+    if (pq < pstep)
+        for (int t = pq; t < 64; t += pstep) {
+            sB[t * TW + wq] =
+                (t < r && wq < tw_n) ? Bbuf[(int64_t)t * bstride + (w0 - w_lo) + wq] : 0ull;
+            sU[t * TW + wq] = 0ull;
+        }
     __syncthreads();
     build_group_tables(sInv, 64, 8, 8, sLT, 1, tid, TU_THREADS);
     const int ng = (r + k - 1) / k;
     const int npass = (ng + tables - 1) / tables;
     const int esz = 1 << k;
     const uint32_t kmask = (1u << k) - 1;
-    const int rows_per_it = TU_THREADS / TW;
-    const int my_w = tid % TW, my_row = tid / TW;
-    for (int pass = 0; pass < npass; pass++) {
-        const int g0 = pass * tables, g1 = min(ng, g0 + tables);
-        build_group_tables(sB + (size_t)g0 * k * TW, r - g0 * k, k, g1 - g0, sT, TW, tid,
-                           TU_THREADS);
-        if (pivots_here) {
-            for (int e = tid; e < r * TW; e += TU_THREADS) {
-                const int t = e / TW, w = e % TW;
-                const uint64_t c = sInv[t];
-                uint64_t x = sU[e];
-                for (int g = g0; g < g1; g++)
-                    x ^= sT[((g - g0) * esz + (int)((c >> (k * g)) & kmask)) * TW + w];
-                sU[e] = x;
-            }
-        }
-        if (my_row < rows_per_it && my_w < tw_n) {
-            for (int i = R1 + blockIdx.x * rows_per_it + my_row; i < m;
-                 i += gridDim.x * rows_per_it) {
-                const uint64_t l = A[(int64_t)i * stride + wc];
-                uint64_t c = 0;
+    const int per = gridDim.x * TU_THREADS;
+    const int nrows = m - R1;
+    const int nchunks = nrows > 0 ? (nrows + per - 1) / per : 1;
+    for (int chunk = 0; chunk < nchunks; chunk++) {
+        const int i = R1 + chunk * per + blockIdx.x * TU_THREADS + tid;
+        const bool act = i < m;
+        uint64_t c = 0;
+        uint64_t x[TU_TWMAX];
+        uint64_t *px = A + (int64_t)i * stride + w0;
+        if (act) {
+            const uint64_t l = A[(int64_t)i * stride + wc];
 #pragma unroll
-                for (int g8 = 0; g8 < 8; g8++) c ^= sLT[g8 * 256 + (int)((l >> (8 * g8)) & 255)];
-                uint64_t *px = A + (int64_t)i * stride + w0 + my_w;
-                uint64_t x = *px;
-                for (int g = g0; g < g1; g++)
-                    x ^= sT[((g - g0) * esz + (int)((c >> (k * g)) & kmask)) * TW + my_w];
-                *px = x;
+            for (int w = 0; w < TU_TWMAX; w++)
+                if (w < tw_n) x[w] = px[w];
+#pragma unroll
+            for (int g8 = 0; g8 < 8; g8++) c ^= sLT[g8 * 256 + (int)((l >> (8 * g8)) & 255)];
+        }
+        for (int pass = 0; pass < npass; pass++) {
+            const int g0 = pass * tables, g1 = min(ng, g0 + tables);
+            if (chunk == 0 || npass > 1) {
+                if (chunk > 0 || pass > 0) __syncthreads();
+                build_group_tables(sB + (size_t)g0 * k * TW, r - g0 * k, k, g1 - g0, sT, TW, tid,
+                                   TU_THREADS);
+                if (pivots_here && chunk == 0 && pq < pstep) {
+                    for (int t = pq; t < r; t += pstep) {
+                        const uint64_t ct = sInv[t];
+                        uint64_t y = sU[t * TW + wq];
+                        for (int g = g0; g < g1; g++)
+                            y ^= sT[((g - g0) * esz + (int)((ct >> (k * g)) & kmask)) * TW + wq];
+                        sU[t * TW + wq] = y;
+                    }
+                }
+            }
+            if (act) {
+                for (int g = g0; g < g1; g++) {
+                    const uint64_t *T = sT + ((size_t)(g - g0) * esz + ((c >> (k * g)) & kmask)) * TW;
+#pragma unroll
+                    for (int w = 0; w < TU_TWMAX; w++)
+                        if (w < tw_n) x[w] ^= T[w];
+                }
             }
         }
-        __syncthreads();
-    }
-    if (pivots_here)
-        for (int e = tid; e < r * TW; e += TU_THREADS) {
-            const int t = e / TW, w = e % TW;
-            if (w < tw_n) A[(int64_t)(R + t) * stride + w0 + w] = sU[e];
+        if (act) {
+#pragma unroll
+            for (int w = 0; w < TU_TWMAX; w++)
+                if (w < tw_n) px[w] = x[w];
         }
+    }
+    if (pivots_here && pq < pstep && wq < tw_n)
+        for (int t = pq; t < r; t += pstep) A[(int64_t)(R + t) * stride + w0 + wq] = sU[t * TW + wq];
 }
 
 hipError_t launch_table_update(uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk,
@@ -293,17 +332,17 @@ hipError_t launch_table_update(uint64_t *A, int64_t stride, int m, int wc, const
     if (w_hi <= w_lo) return hipSuccess;
     int TW = table_update_tile_words(k, tables);
     if (TW > w_hi - w_lo) TW = w_hi - w_lo;
-    int ny = (w_hi - w_lo + TW - 1) / TW;
-    int rows_per_it = TU_THREADS / TW;
-    int nx = (m + rows_per_it - 1) / rows_per_it;
-    int want = (target_blocks + ny - 1) / ny;
-    if (nx > want) nx = want;
+    const int ny = (w_hi - w_lo + TW - 1) / TW;
+    const size_t lds = table_update_lds_bytes(k, tables, TW);
+    const int occ = std::max(1, (int)(CU_LDS / lds));
+    int nx = (m + TU_THREADS - 1) / TU_THREADS;
+    const int fit = std::max(1, target_blocks * occ / ny);
+    if (nx > fit) nx = fit;
     if (nx < 1) nx = 1;
-    size_t lds = table_update_lds_bytes(k, tables, TW);
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void *)table_update_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, TU_LDS_MAX);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
