@@ -117,6 +117,40 @@ size_t gf2_rref_workspace_bytes(int64_t m, int64_t n);
 int gf2_rref(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int32_t *rank,
              gf2_mat R_out, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * Batched PLS: `count` independent matrices of any shapes up to
+ * GF2_BATCH_MAX_M x GF2_BATCH_MAX_N, each decomposed in place exactly as
+ * gf2_pls does (the result of Gaussian PLS, Appendix A).  One persistent launch
+ * serves them all: a block of the device takes one matrix at a time, largest
+ * estimated cost first, and runs the MMPF base case of Section 4.1 over all of
+ * its columns (so a schedule's cutoff and schur fields are ignored here).
+ *  items     DEVICE array of count descriptors; every words/P/Q pointer is device
+ *            memory; matrices must not overlap each other or any P/Q array.
+ *  ranks     DEVICE int32[count]: the rank of item j, or GF2_E_ARG (negative) if
+ *            item j is invalid (size out of range, stride too small, null or
+ *            misaligned pointer); an invalid item's buffers are not touched.
+ *  per_item  DEVICE gf2_sched[count] or NULL: k and tables of item j; an entry
+ *            with k or tables out of range falls back to `s`.
+ *  s         HOST schedule for every item without its own (NULL: default).
+ * The call enqueues a fixed sequence of kernels and allocates nothing, so it can
+ * be captured into a HIP graph and replayed (inputs restored between replays).
+ */
+#define GF2_BATCH_MAX_N 4096
+#define GF2_BATCH_MAX_M (1 << 24)
+
+typedef struct gf2_batch_item {
+    uint64_t *words;
+    int64_t m, n;
+    int64_t stride;
+    int32_t *P;
+    int32_t *Q;
+} gf2_batch_item;
+
+size_t gf2_pls_batched_workspace_bytes(int64_t count);
+int gf2_pls_batched(gf2_ctx *ctx, const gf2_batch_item *items, int64_t count, int32_t *ranks,
+                    const gf2_sched *per_item, const gf2_sched *s, void *ws, size_t ws_bytes,
+                    void *stream);
+
 /* Workspace bytes gf2_addmul needs for C (m x n) += A (m x k) * B (k x n). */
 size_t gf2_addmul_workspace_bytes(int64_t m, int64_t k, int64_t n);
 

@@ -18,7 +18,7 @@ import torch
 from .build import LIB as _LIB_PATH
 
 __all__ = ["Sched", "Mat", "get_lib", "default_sched", "pls", "rref", "addmul", "to_device",
-           "to_host", "workspace", "SCHUR_XOR", "SCHUR_MFMA", "GF2Error"]
+           "to_host", "workspace", "Batch", "SCHUR_XOR", "SCHUR_MFMA", "GF2Error"]
 
 SCHUR_XOR = 0
 SCHUR_MFMA = 1
@@ -42,6 +42,11 @@ class Sched(ctypes.Structure):
 
     def __repr__(self):
         return f"Sched(k={self.k}, tables={self.tables}, cutoff={self.cutoff}, schur={self.schur})"
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("words", ctypes.c_void_p), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("stride", ctypes.c_int64), ("P", ctypes.c_void_p), ("Q", ctypes.c_void_p)]
 
 
 class ProfStats(ctypes.Structure):
@@ -77,6 +82,10 @@ def _load():
     L.gf2_rref_workspace_bytes.restype = sz
     L.gf2_rref.argtypes = [vp, Mat, vp, vp, Mat, vp, sz, vp]
     L.gf2_rref.restype = i32
+    L.gf2_pls_batched_workspace_bytes.argtypes = [i64]
+    L.gf2_pls_batched_workspace_bytes.restype = sz
+    L.gf2_pls_batched.argtypes = [vp, vp, i64, vp, vp, ctypes.POINTER(Sched), vp, sz, vp]
+    L.gf2_pls_batched.restype = i32
     L.gf2_addmul_workspace_bytes.argtypes = [i64, i64, i64]
     L.gf2_addmul_workspace_bytes.restype = sz
     L.gf2_addmul.argtypes = [vp, Mat, Mat, Mat, i32, vp, sz, vp]
@@ -184,6 +193,72 @@ def pls(A: torch.Tensor, m: int, n: int, s: Sched | None = None, ws: torch.Tenso
                        ctypes.byref(s) if s is not None else None, ws.data_ptr(), ws.numel(),
                        _stream(stream)))
     return P[:m], Q[:n], rank
+
+
+class Batch:
+    """Descriptors for gf2_pls_batched over a list of device matrices.
+
+    mats[j] is an int64 CUDA tensor (m_j, stride_j) factored in place; the
+    descriptors, P/Q buffers, ranks and workspace are allocated here once, so
+    that ``run`` enqueues kernels only (and can be captured into a graph).
+    """
+
+    def __init__(self, mats, shapes, device=None):
+        if len(mats) != len(shapes):
+            raise ValueError("one shape per matrix")
+        dev = torch.device(device) if device is not None else (
+            mats[0].device if mats else torch.device("cuda"))
+        self.device = dev
+        self.count = len(mats)
+        self.shapes = [(int(m), int(n)) for m, n in shapes]
+        self.p_off, self.q_off = [], []
+        pm = pn = 0
+        for m, n in self.shapes:
+            self.p_off.append(pm)
+            self.q_off.append(pn)
+            pm += m
+            pn += n
+        self.P = torch.empty(max(pm, 1), dtype=torch.int32, device=dev)
+        self.Q = torch.empty(max(pn, 1), dtype=torch.int32, device=dev)
+        arr = (BatchItem * max(self.count, 1))()
+        for j, (t, (m, n)) in enumerate(zip(mats, self.shapes)):
+            if t.dtype != torch.int64 or not t.is_cuda or t.dim() != 2 or not t.is_contiguous():
+                raise ValueError("matrix must be a contiguous 2-D int64 CUDA tensor")
+            if t.shape[0] != m:
+                raise ValueError("row count mismatch")
+            arr[j] = BatchItem(t.data_ptr(), m, n, t.shape[1],
+                               self.P.data_ptr() + 4 * self.p_off[j],
+                               self.Q.data_ptr() + 4 * self.q_off[j])
+        raw = bytes(arr)
+        self.items = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
+        self.ranks = torch.empty(max(self.count, 1), dtype=torch.int32, device=dev)
+        nb = int(get_lib().gf2_pls_batched_workspace_bytes(self.count))
+        self.ws = workspace(nb, dev)
+        self.per_item = None
+        self.mats = list(mats)
+
+    def set_scheds(self, scheds):
+        """Per-matrix schedules (Sched or (k, tables, cutoff, schur) tuples); None clears."""
+        if scheds is None:
+            self.per_item = None
+            return
+        rows = [x.astuple() if isinstance(x, Sched) else tuple(x) for x in scheds]
+        if len(rows) != self.count:
+            raise ValueError("one schedule per matrix")
+        self.per_item = torch.tensor(rows, dtype=torch.int32).to(self.device)
+
+    def run(self, s: Sched | None = None, stream=None):
+        """Enqueue the batched decomposition (asynchronous)."""
+        per = self.per_item.data_ptr() if self.per_item is not None else None
+        _check(get_lib().gf2_pls_batched(ctx(self.device.index), self.items.data_ptr(), self.count,
+                                         self.ranks.data_ptr(), per,
+                                         ctypes.byref(s) if s is not None else None,
+                                         self.ws.data_ptr(), self.ws.numel(), _stream(stream)))
+        return self.ranks[:self.count]
+
+    def pq(self, j: int):
+        m, n = self.shapes[j]
+        return (self.P[self.p_off[j]:self.p_off[j] + m], self.Q[self.q_off[j]:self.q_off[j] + n])
 
 
 def rref_workspace_bytes(m: int, n: int) -> int:

@@ -32,6 +32,7 @@ struct ProfRec {
 struct gf2_ctx {
     int device;
     int cus;
+    int batch_bpc = 1;   // resident blocks per CU of the batched kernel
     int32_t *plog = nullptr;
     int64_t plog_cap = 0;
     std::vector<ProfRec> recs;
@@ -276,9 +277,11 @@ int gf2_ctx_create(gf2_ctx **out, int device) {
     if (device < 0 || device >= count) return GF2_E_ARG;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return GF2_E_HIP;
+    if (hipSetDevice(device) != hipSuccess) return GF2_E_HIP;
     gf2_ctx *c = new gf2_ctx;
     c->device = device;
     c->cus = prop.multiProcessorCount;
+    c->batch_bpc = batch_blocks_per_cu();
     *out = c;
     return GF2_OK;
 }
@@ -411,6 +414,29 @@ int gf2_pls(gf2_ctx *ctx, gf2_mat A, int32_t *P, int32_t *Q, int32_t *rank, cons
     else d.chk(launch_fill_i32(d.rk, 0, d.nb + 1, st));
     d.chk(launch_finalize(P, Q, rank, d.rk, d.nb, d.m, d.n, st));
     return d.err == hipSuccess ? GF2_OK : GF2_E_HIP;
+}
+
+size_t gf2_pls_batched_workspace_bytes(int64_t count) {
+    if (count < 0) return 0;
+    return align_up(batch_ws_bytes(count));
+}
+
+int gf2_pls_batched(gf2_ctx *ctx, const gf2_batch_item *items, int64_t count, int32_t *ranks,
+                    const gf2_sched *per_item, const gf2_sched *s, void *ws, size_t ws_bytes,
+                    void *stream) {
+    if (!ctx || count < 0 || count > (int64_t)1 << 30) return GF2_E_ARG;
+    if (count == 0) return GF2_OK;
+    if (!items || !ranks) return GF2_E_ARG;
+    gf2_sched ss = s ? *s : default_sched();
+    if (!sched_ok(&ss)) return GF2_E_ARG;
+    if (!ws || ws_bytes < gf2_pls_batched_workspace_bytes(count)) return GF2_E_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0 || ((uintptr_t)items & 7) != 0 || ((uintptr_t)ranks & 3) != 0)
+        return GF2_E_ALIGN;
+    if (hipSetDevice(ctx->device) != hipSuccess) return GF2_E_HIP;
+    const int64_t grid = std::min<int64_t>(count, (int64_t)ctx->cus * ctx->batch_bpc);
+    hipError_t e = launch_pls_batched(items, (int)count, ranks, per_item, ss, (int32_t *)ws,
+                                      (int)grid, (hipStream_t)stream);
+    return e == hipSuccess ? GF2_OK : GF2_E_HIP;
 }
 
 }  // extern "C"

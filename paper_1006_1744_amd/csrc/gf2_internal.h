@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/gf2pls.h"
+
 namespace gf2 {
 
 // Row range [start, end) with start = rk[ib] + a and
@@ -135,4 +137,11 @@ hipError_t launch_rref_scatter(uint64_t *R, int64_t sr, int m, int n, const int3
                                const uint64_t *NM, const int32_t *prefN, const uint64_t *Xc,
                                int64_t sx, hipStream_t st);
 
+// Batched PLS (k_batch.hip): queue order, then one persistent launch of `grid`
+// blocks.  ws holds batch_ws_bytes(count) bytes.
+size_t batch_ws_bytes(int64_t count);
+int batch_blocks_per_cu();
+hipError_t launch_pls_batched(const gf2_batch_item *items, int count, int32_t *ranks,
+                              const gf2_sched *per, gf2_sched def, int32_t *ws, int grid,
+                              hipStream_t st);
 }  // namespace gf2

@@ -1,0 +1,415 @@
+// The panel search of the MMPF base case (PlsSubmatrix, Appendix A), as a
+// device function shared by the single-matrix panel kernel and the batched
+// kernel: PLS of one 64-column panel (one word column) of the rows [R, m),
+// with the pivot rule of Gaussian PLS (Appendix A): smallest column with a one
+// among the remaining rows, first such row in the current order, transposition
+// swap; additions keep the multiplier bit (L) in place.
+//
+// PlsSubmatrix re-planned for one CU of gfx950:
+//  * The search touches a window of LEAF_W rows held in registers of wave 0
+//    (LEAF_H rows per lane); a column test is one 64-lane ballot per register
+//    and the first set lane (ffs) is the first row in the current order.
+//  * Window rows are reduced eagerly by each new pivot (one masked XOR).
+//  * Rows past the window frontier F are reduced lazily, as PlsSubmatrix's
+//    done[] bookkeeping does: the pivots [pa, t) found since they were last
+//    touched ("pending") are kept as Gray-style tables (MakeTable1 with the
+//    a-priori-id fix, Section 4.1) of 8 pivots each in LDS, and applied when a
+//    row enters the window, is scanned by a far search, or in the final pass.
+//  * If no window row has a one in the current column, a block-wide far search
+//    scans the rows past the window in order and stops at the first hit.
+// The final pass (pending tables for rows >= F, the panel's "compress L"
+// column swaps) and the moves of the pivot rows' other words follow the search.
+#pragma once
+
+#include <stddef.h>
+
+#include "gf2_device.h"
+#include "gf2_internal.h"
+
+namespace gf2 {
+
+
+constexpr int LEAF_THREADS = 256;
+constexpr int LEAF_H = 2;
+constexpr int LEAF_W = 64 * LEAF_H;
+
+// Per-panel record written by the search and read by the passes after it.
+struct PanelInfo {
+    int32_t r;       // pivots found
+    int32_t F;       // rows at offsets >= F still lack pivots [pa, r)
+    int32_t pa;      // first pending pivot
+    int32_t compress;// non-zero if some pivot column differs from its index
+    int32_t q[64];   // pivot columns relative to the panel
+    uint64_t u[64];  // pivot rows' panel words when chosen (reduced by earlier pivots)
+    uint64_t linv[64];  // rows of L^{-1} for the panel's r x r unit lower triangle
+    int32_t moved[kMovedInts];
+#ifdef GF2_TRACE
+    uint64_t trace[16];
+#endif
+};
+
+// Build tables for pivots [ta, tb) (consecutive columns q[ta], q[ta]+1, ...):
+// group g holds pivots ta+8g .. ; entry [key] added to a row whose group bits
+// read `key` clears them to the multipliers and reduces the bits above.
+__device__ inline void build_tables(const uint64_t *U, const int32_t *q, int ta, int tb,
+                             uint64_t (*T)[256], int tid, int nthr) {
+    int np = tb - ta;
+    int ng = (np + 7) >> 3;
+    for (int e = tid; e < ng * 256; e += nthr) {
+        int g = e >> 8, comb = e & 255;
+        int gs = min(8, np - 8 * g);
+        if (comb >= (1 << gs)) continue;
+        uint64_t v = 0;
+        for (int u = 0; u < gs; u++) {
+            if ((comb >> u) & 1) {
+                int s = ta + 8 * g + u;
+                v ^= U[s] & (~0ull << q[s]);
+            }
+        }
+        int off = q[ta] + 8 * g;
+        int key = (int)((v >> off) & ((1u << gs) - 1));
+        T[g][key] = v ^ ((uint64_t)comb << off);
+    }
+}
+
+__device__ inline uint64_t apply_tables(uint64_t x, const int32_t *q, int ta, int tb,
+                                        const uint64_t (*T)[256]) {
+    int np = tb - ta;
+    int base = np > 0 ? q[ta] : 0;
+    for (int g = 0; 8 * g < np; g++) {
+        int gs = min(8, np - 8 * g);
+        int off = base + 8 * g;
+        int key = (int)((x >> off) & ((1u << gs) - 1));
+        x ^= T[g][key];
+    }
+    return x;
+}
+
+// Value v (wave-uniform) written into lane l of a per-lane register.
+__device__ inline uint64_t writelane64(uint64_t old, uint64_t v, int l) {
+    return (int)__lane_id() == l ? v : old;
+}
+
+__device__ inline int writelane32(int v, int l, int old) {
+    return (int)__lane_id() == l ? v : old;
+}
+
+
+// LDS of one search (all threads of a 256-thread block take part).
+struct SearchLds {
+    uint64_t sU[64];
+    int32_t sQ[64];
+    int32_t sPrel[64];
+    uint64_t sT[8][256];   // pending pivots [pa, t), for rows >= F
+    uint64_t sE[8][256];   // pivots of the last epoch, for rows in [window end, F)
+    int s_t, s_c, s_F, s_pa, s_brk, s_far, s_tab_lo, s_tab_hi, s_epochs;
+    int sOg[LEAF_W];       // first window: original offset of each entry's row
+};
+
+// Search of the panel at word column wc over rows [R, m).  Writes P and Q at
+// the pivot slots R + t, the window rows' and scanned rows' panel words, and
+// *info (r, F, pa, compress, q, u, linv, moved).  Returns r (in every thread).
+__device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, int wc, int R,
+                                   int32_t *P, int32_t *Q, PanelInfo *info, SearchLds &S) {
+    uint64_t *sU = S.sU;
+    int32_t *sQ = S.sQ;
+    int32_t *sPrel = S.sPrel;
+    uint64_t (*sT)[256] = S.sT;
+    uint64_t (*sE)[256] = S.sE;
+    int &s_t = S.s_t, &s_c = S.s_c, &s_F = S.s_F, &s_pa = S.s_pa, &s_brk = S.s_brk;
+    int &s_far = S.s_far, &s_tab_lo = S.s_tab_lo, &s_tab_hi = S.s_tab_hi, &s_epochs = S.s_epochs;
+    int *sOg = S.sOg;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int mrem = m - R;
+    const int nc = min(64, n - 64 * wc);
+    uint64_t *col = A + (int64_t)R * stride + wc;
+    const int NOHIT = 0x7fffffff;
+    bool simple = true;      // one window, no far search: moves read off sOg[]
+
+#ifdef GF2_TRACE
+    int ntr = 0;
+#define TR() do { if (tid == 0 && ntr < 14) { info->trace[ntr++] = __builtin_amdgcn_s_memrealtime(); info->trace[ntr++] = __builtin_amdgcn_s_memtime(); } } while (0)
+#else
+#define TR() do {} while (0)
+#endif
+    TR();
+    if (tid == 0) {
+        s_t = 0; s_c = 0; s_F = 0; s_pa = 0; s_tab_lo = -1; s_tab_hi = -1; s_brk = 0;
+        s_far = NOHIT; s_epochs = 0;
+    }
+    __syncthreads();
+
+    // Invariant at the top of each round: rows at offsets [t, F) are reduced by
+    // every pivot found so far; rows >= F are reduced by pivots [0, pa) only.
+    while (true) {
+        const int t = s_t, c = s_c, F = s_F, pa = s_pa, tl = s_tab_lo, th = s_tab_hi;
+        const int epochs = s_epochs;
+        __syncthreads();
+        if (mrem <= 0 || c >= nc || t >= mrem) break;
+        if (epochs > 0) simple = false;
+        const bool need_tab = F < mrem && t > pa && (tl != pa || th != t);
+        if (need_tab) build_tables(sU, sQ, pa, t, sT, tid, LEAF_THREADS);
+        __syncthreads();
+        if (need_tab && tid == 0) { s_tab_lo = pa; s_tab_hi = t; }
+        const int ts = t;
+        if (wave == 0) {
+            // Window: entries e = lane and 64 + lane hold the rows at offsets ts + e,
+            // all reduced by every pivot found so far.  The search works on the
+            // transpose: lane j holds column j of the window as two 64-bit words
+            // (bit e = entry e), so a column's candidates are one readlane and a
+            // row operation is one masked XOR per lane.
+            const int o0 = ts + lane, o1 = ts + 64 + lane;
+            uint64_t x0 = o0 < mrem ? col[(int64_t)o0 * stride] : 0ull;
+            uint64_t x1 = o1 < mrem ? col[(int64_t)o1 * stride] : 0ull;
+            if (t > pa) {
+                if (o0 < mrem && o0 >= F) x0 = apply_tables(x0, sQ, pa, t, sT);
+                if (o1 < mrem && o1 >= F) x1 = apply_tables(x1, sQ, pa, t, sT);
+            }
+            int og0 = o0, og1 = o1;
+            uint64_t m0 = __ballot(o0 < mrem), m1 = __ballot(o1 < mrem);   // candidates
+            TR();
+            uint64_t c0 = transpose64(x0, lane), c1 = transpose64(x1, lane);
+            TR();
+            int fer = -1;   // lane j: window entry of the pivot of column j (this epoch)
+            int tt = t, cc = c, brk = 0;
+            while (true) {
+                cc = __builtin_amdgcn_readfirstlane(cc);
+                tt = __builtin_amdgcn_readfirstlane(tt);
+                if (cc >= nc || tt >= mrem) break;
+                const uint64_t b0 = readlane64(c0, cc) & m0;
+                const uint64_t b1 = readlane64(c1, cc) & m1;
+                if ((b0 | b1) == 0) {
+                    if (ts + LEAF_W >= mrem) { cc++; continue; }  // zero in every remaining row
+                    brk = 1;
+                    break;
+                }
+                // first candidate with a one: entry fe = fl (+ 64 if in the second half)
+                const bool in1 = b0 == 0;
+                const uint64_t bb = in1 ? b1 : b0;
+                const int fl = __ffsll((unsigned long long)bb) - 1;
+                const int fe = fl + (in1 ? 64 : 0);
+                const int es = tt - ts;   // < 64: pivots fill the window from its start
+                const uint64_t fbit = 1ull << fl;
+                // rows with a one in column cc other than the pivot add the pivot row on
+                // the columns right of cc: column j > cc flips them where the pivot has a one
+                const uint64_t E0 = in1 ? b0 : (b0 & ~fbit);
+                const uint64_t E1 = in1 ? (b1 & ~fbit) : b1;
+                const uint64_t src = in1 ? c1 : c0;
+                const bool flip = lane > cc && ((src >> fl) & 1ull);
+                c0 ^= flip ? E0 : 0ull;
+                c1 ^= flip ? E1 : 0ull;
+                // transposition of entries es and fe (no-op when equal)
+                const uint64_t src2 = in1 ? c1 : c0;
+                const uint64_t d = ((c0 >> es) ^ (src2 >> fl)) & 1ull;
+                c0 ^= (d << es) ^ (in1 ? 0ull : (d << fl));
+                c1 ^= in1 ? (d << fl) : 0ull;
+                const int ogs = __builtin_amdgcn_readlane(og0, es);
+                const int oge = in1 ? __builtin_amdgcn_readlane(og1, fl)
+                                    : __builtin_amdgcn_readlane(og0, fl);
+                og0 = lane == es ? oge : og0;
+                og0 = (!in1 && lane == fl) ? ogs : og0;
+                og1 = (in1 && lane == fl) ? ogs : og1;
+                fer = lane == cc ? fe : fer;
+                m0 &= ~(1ull << es);
+                tt++;
+                cc++;
+            }
+            TR();
+            x0 = transpose64(c0, lane);
+            x1 = transpose64(c1, lane);
+            if (o0 < mrem) col[(int64_t)o0 * stride] = x0;
+            if (o1 < mrem) col[(int64_t)o1 * stride] = x1;
+            TR();
+            // bookkeeping of the pivots [t, tt), one lane per column
+            const uint64_t isp = __ballot(fer >= 0);
+            if (fer >= 0) {
+                const int pidx = t + __popcll(isp & ((1ull << lane) - 1));
+                P[R + pidx] = R + ts + fer;
+                Q[R + pidx] = 64 * wc + lane;
+                sQ[pidx] = lane;
+                sPrel[pidx] = ts + fer;
+            }
+            if (lane < tt - t) sU[t + lane] = x0;   // pivot rows stay where they were put
+            if (epochs == 0) {
+                sOg[lane] = og0;
+                sOg[64 + lane] = og1;
+            }
+            if (lane == 0) {
+                s_t = tt;
+                s_c = cc;
+                s_brk = brk;
+                s_epochs = epochs + 1;
+                const int nF = max(F, min(ts + LEAF_W, mrem));
+                s_F = nF;
+                if (nF >= mrem) s_pa = tt;   // no row is left past the frontier
+            }
+        }
+        __syncthreads();
+        const int t1 = s_t, c1 = s_c, brk = s_brk;
+        __syncthreads();
+        // Rows between the window and an older frontier miss this epoch's pivots.
+        const int wend = min(ts + LEAF_W, mrem);
+        if (t1 > ts && F > wend) {
+            build_tables(sU, sQ, ts, t1, sE, tid, LEAF_THREADS);
+            __syncthreads();
+            for (int o = wend + tid; o < F; o += LEAF_THREADS)
+                col[(int64_t)o * stride] = apply_tables(col[(int64_t)o * stride], sQ, ts, t1, sE);
+            __syncthreads();
+        }
+        if (!brk || t1 > ts) continue;
+        // Far search: no window row has a one in column c1.  Scan the rows past
+        // the window in order, bringing rows >= F up to date, and stop after the
+        // first block-sized chunk holding a hit.
+        simple = false;
+        const int F2 = s_F, pa2 = s_pa, tl2 = s_tab_lo, th2 = s_tab_hi;
+        __syncthreads();
+        const bool need2 = F2 < mrem && t1 > pa2 && (tl2 != pa2 || th2 != t1);
+        if (need2) build_tables(sU, sQ, pa2, t1, sT, tid, LEAF_THREADS);
+        if (tid == 0) s_far = NOHIT;
+        __syncthreads();
+        if (need2 && tid == 0) { s_tab_lo = pa2; s_tab_hi = t1; }
+        int scan_end = wend;
+        for (int base = wend; base < mrem; base += LEAF_THREADS) {
+            const int o = base + tid;
+            if (o < mrem) {
+                uint64_t v = col[(int64_t)o * stride];
+                if (o >= F2 && t1 > pa2) {
+                    v = apply_tables(v, sQ, pa2, t1, sT);
+                    col[(int64_t)o * stride] = v;
+                }
+                if ((v >> c1) & 1) atomicMin(&s_far, o);
+            }
+            scan_end = min(base + LEAF_THREADS, mrem);
+            __syncthreads();
+            const bool hit = s_far != NOHIT;
+            __syncthreads();
+            if (hit) break;
+        }
+        const int f = s_far;
+        const int F3 = max(F2, scan_end);
+        if (f == NOHIT) {
+            // column c1 is zero in every remaining row; every row is reduced now
+            if (tid == 0) { s_c = c1 + 1; s_F = F3; s_pa = t1; }
+            __syncthreads();
+            continue;
+        }
+        if (tid == 0) {
+            uint64_t pw = col[(int64_t)f * stride];
+            uint64_t tw = col[(int64_t)t1 * stride];
+            col[(int64_t)t1 * stride] = pw;
+            col[(int64_t)f * stride] = tw;
+            sU[t1] = pw;
+            sQ[t1] = c1;
+            sPrel[t1] = f;
+            P[R + t1] = R + f;
+            Q[R + t1] = 64 * wc + c1;
+        }
+        __syncthreads();
+        {
+            // rows after f up to the new frontier may hold a one in column c1
+            const uint64_t pw = sU[t1];
+            const uint64_t above = c1 == 63 ? 0ull : (~0ull << (c1 + 1));
+            for (int o = f + 1 + tid; o < F3; o += LEAF_THREADS) {
+                uint64_t v = col[(int64_t)o * stride];
+                if ((v >> c1) & 1) col[(int64_t)o * stride] = v ^ (pw & above);
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            s_t = t1 + 1;
+            s_c = c1 + 1;
+            s_F = F3;
+            s_pa = F3 >= mrem ? t1 + 1 : pa2;
+            s_epochs = 2;   // moved rows no longer follow from one window
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+
+    TR();
+    const int r = max(0, min(s_t, mrem));
+    if (wave == 0) {
+        int32_t *mv = info->moved;
+        if (simple) {
+            // one window starting at offset 0: entry e holds the row from sOg[e]
+            int base_cnt = 0;
+#pragma unroll
+            for (int h = 0; h < LEAF_H; h++) {
+                const int e = lane + 64 * h;
+                const int og = sOg[e];
+                const bool mvd = og != e && e < mrem;
+                const uint64_t bal = __ballot(mvd);
+                const int idx = base_cnt + __popcll(bal & ((1ull << lane) - 1));
+                if (mvd) { mv[1 + 2 * idx] = e; mv[2 + 2 * idx] = og; }
+                base_cnt += __popcll(bal);
+            }
+            if (lane == 0) mv[0] = base_cnt;
+        } else {
+            // compose the transpositions (s, sPrel[s]) into (position, source) pairs;
+            // lane holds list entries lane and lane + 64
+            int pos0 = -1, src0 = 0, pos1 = -1, src1 = 0;
+            int nk = 0;
+            for (int s2 = 0; s2 < r; s2++) {
+                const int a = s2, qq = sPrel[s2];
+                if (a == qq) continue;
+                const uint64_t ba = __ballot(pos0 == a), ba1 = __ballot(pos1 == a);
+                const uint64_t bq = __ballot(pos0 == qq), bq1 = __ballot(pos1 == qq);
+                const int ia = ba ? __ffsll((unsigned long long)ba) - 1
+                                  : (ba1 ? 64 + __ffsll((unsigned long long)ba1) - 1 : -1);
+                const int iq = bq ? __ffsll((unsigned long long)bq) - 1
+                                  : (bq1 ? 64 + __ffsll((unsigned long long)bq1) - 1 : -1);
+                int sa = a, sq = qq;
+                if (ia >= 0)
+                    sa = ia < 64 ? __builtin_amdgcn_readlane(src0, ia)
+                                 : __builtin_amdgcn_readlane(src1, ia - 64);
+                if (iq >= 0)
+                    sq = iq < 64 ? __builtin_amdgcn_readlane(src0, iq)
+                                 : __builtin_amdgcn_readlane(src1, iq - 64);
+                // position a now holds the row that was at qq, and qq the one at a
+                const int slot_a = ia >= 0 ? ia : nk;
+                if (ia < 0) nk++;
+                const int slot_q = iq >= 0 ? iq : nk;
+                if (iq < 0) nk++;
+                if (slot_a < 64) { if (lane == slot_a) { pos0 = a; src0 = sq; } }
+                else if (lane == slot_a - 64) { pos1 = a; src1 = sq; }
+                if (slot_q < 64) { if (lane == slot_q) { pos0 = qq; src0 = sa; } }
+                else if (lane == slot_q - 64) { pos1 = qq; src1 = sa; }
+            }
+            if (lane == 0) mv[0] = nk;
+            if (lane < nk) { mv[1 + 2 * lane] = pos0; mv[2 + 2 * lane] = src0; }
+            if (lane + 64 < nk) { mv[1 + 2 * (lane + 64)] = pos1; mv[2 + 2 * (lane + 64)] = src1; }
+        }
+        TR();
+        // L (r x r, pivot order): L[t][s] is bit q[s] of the pivot word sU[t].
+        // Lane j solves L x = e_j column by column (x ^= L[:, s] where x[s] = 1),
+        // then the columns of L^{-1} are transposed into rows.  Identity past r.
+        const uint64_t urow = lane < r ? sU[lane] : 0ull;
+        uint64_t xcol = 1ull << lane;
+        for (int s2 = 0; s2 + 1 < r; s2++) {
+            const int qs = sQ[s2];
+            const uint64_t Lcol = __ballot(lane > s2 && lane < r && ((urow >> qs) & 1ull));
+            if ((xcol >> s2) & 1ull) xcol ^= Lcol;
+        }
+        info->linv[lane] = transpose64(xcol, lane);
+        info->q[lane] = lane < r ? sQ[lane] : lane;
+        info->u[lane] = urow;
+    }
+    if (tid == 0) {
+        int cmp = 0;
+        for (int s2 = 0; s2 < r; s2++) cmp |= (sQ[s2] != s2);
+        info->r = r;
+        info->F = max(0, min(s_F, mrem));
+        info->pa = min(s_pa, r);
+        info->compress = cmp;
+    }
+    TR();
+#ifdef GF2_TRACE
+    if (tid == 0) info->trace[15] = ntr;
+#endif
+    __syncthreads();
+    return r;
+}
+
+
+}  // namespace gf2

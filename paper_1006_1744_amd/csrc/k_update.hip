@@ -352,35 +352,8 @@ hipError_t launch_table_update(uint64_t *A, int64_t stride, int m, int wc, const
 }
 
 // ---------------------------------------------------------- compress shift
-// Node at column c0 with split n0 (both multiples of 64): the second block's L
-// columns [c0+n0, c0+n0+r1) move to [c0+r0, c0+r0+r1), row by row as the column
-// swaps "i <-> n0 + (i - r0), from row i" leave them: a row at offset v below
-// the first block's pivots moves min(v + 1, r1) columns and zeroes the vacated ones.
-__device__ inline void shift_row(uint64_t *row, int64_t stride, int c0, int n0, int r0, int r1,
-                                 int v) {
-    const int d = n0 - r0;
-    const int len = min(v + 1, r1);
-    const int D = c0 + r0;             // first destination bit
-    const int S = c0 + n0;             // first source bit
-    const int end = S + len;           // bits [D, end) change
-    for (int w = D >> 6; w <= (end - 1) >> 6; w++) {
-        const int p0 = w * 64;
-        const int sb = p0 + d;         // source of position p0
-        const int sw = sb >> 6, so = sb & 63;
-        const uint64_t lo = sw < stride ? row[sw] : 0ull;
-        const uint64_t hi = (so && sw + 1 < stride) ? row[sw + 1] : 0ull;
-        const uint64_t src = so ? ((lo >> so) | (hi << (64 - so))) : lo;
-        const uint64_t old = row[w];
-        uint64_t mv = 0, clr = 0;
-        int a = max(D, p0), e = min(D + len, p0 + 64);
-        if (e > a) mv = ((e - a) == 64 ? ~0ull : ((1ull << (e - a)) - 1)) << (a - p0);
-        a = max(D + len, p0);
-        e = min(end, p0 + 64);
-        if (e > a) clr = ((e - a) == 64 ? ~0ull : ((1ull << (e - a)) - 1)) << (a - p0);
-        row[w] = (old & ~(mv | clr)) | (src & mv);
-    }
-}
-
+// Node at column c0 with split n0: every row below the first block's pivots
+// takes its part of the "compress L" move (shift_row).
 __global__ void compress_shift_kernel(uint64_t *A, int64_t stride, int m, int c0, int n0,
                                       const int32_t *rk, int b0, int b1, int b2) {
     const int R = rk[b0], Rm = rk[b1], Re = rk[b2];
