@@ -151,6 +151,76 @@ int gf2_pls_batched(gf2_ctx *ctx, const gf2_batch_item *items, int64_t count, in
                     const gf2_sched *per_item, const gf2_sched *s, void *ws, size_t ws_bytes,
                     void *stream);
 
+/*
+ * Autotuner (schedules only; a schedule never changes a result bit).
+ * gf2_sched_candidates: the deduplicated candidate schedules for an m x n
+ *   problem: k in 4..8 x tables in {1,2,4,8} x cutoff in {256,512,1024,2048,4096}
+ *   x schur in {XOR, MFMA}, where all cutoffs at or above the padded width
+ *   collapse into one MMPF-only candidate (no Schur product is formed); with
+ *   batched != 0, k x tables only (the batched call ignores cutoff and schur).
+ *   Writes up to max entries (host array) and returns the total count, or a
+ *   negative status.
+ * gf2_autotune: runs gf2_pls once per repetition for every candidate on
+ *   A_work after copying the pristine A_trial into it (same m, n; A_trial is only
+ *   read), times each run with HIP events on `stream` and waits for them.
+ *   ms_out[i] (host) receives candidate i's fastest time and *best the fastest
+ *   candidate (the default schedule when ncand == 0).  The workspace must hold
+ *   gf2_autotune_workspace_bytes(m, n, cands, ncand) bytes (256-byte aligned).
+ * gf2_autotune_batched: the same for gf2_pls_batched on a batch of trial items
+ *   (device descriptors `trial`, copied into the same-shaped `work` items before
+ *   each run; ranks is a device int32[count]); workspace as gf2_pls_batched.
+ * Not graph-capturable (the calls wait for their events).
+ */
+int gf2_sched_candidates(int64_t m, int64_t n, int batched, gf2_sched *out, int max);
+size_t gf2_autotune_workspace_bytes(int64_t m, int64_t n, const gf2_sched *cands, int ncand);
+int gf2_autotune(gf2_ctx *ctx, gf2_mat A_trial, gf2_mat A_work, const gf2_sched *cands, int ncand,
+                 int reps, float *ms_out, gf2_sched *best, void *ws, size_t ws_bytes, void *stream);
+int gf2_autotune_batched(gf2_ctx *ctx, const gf2_batch_item *trial, const gf2_batch_item *work,
+                         int64_t count, int32_t *ranks, const gf2_sched *cands, int ncand, int reps,
+                         float *ms_out, gf2_sched *best, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Learned cost model: an fp32 network 4 -> 64 -> 64 -> S (ReLU) predicting the
+ * log run time of each of S candidate schedules from a problem's features; the
+ * predicted schedule is the argmin (the field-operation count alone mispredicts
+ * run time, Section 1).  It only chooses schedules and never touches the
+ * arithmetic.
+ *  params  DEVICE fp32[gf2_mlp_param_count(S)]: W1[4][64] b1[64] W2[64][64]
+ *          b2[64] W3[64][S] b3[S], W[a][j] from input a to output j.
+ *  feats   DEVICE fp32[N][4] raw features: log2 m, log2 n, density, rank
+ *          estimate / min(m, n); the network scales them to (f0/16, f1/16, f2, f3).
+ * gf2_mlp_init: uniform(-sqrt(6/fan_in), +sqrt(6/fan_in)) weights from SplitMix64
+ *   draws at the parameter index, zero biases.
+ * gf2_mlp_forward: out (DEVICE fp32[N][S]) = predicted log times.
+ * gf2_mlp_grad: loss = inv_count * sum of mask[i][s] (out[i][s] - target[i][s])^2
+ *   over DEVICE fp32[N][S] target and mask; grad (DEVICE fp32[P + 1]) receives
+ *   d loss / d params, then the loss.  Sums run in a fixed order (deterministic).
+ *   Workspace: gf2_mlp_grad_workspace_bytes(S, N).
+ * gf2_mlp_adam: one Adam step (Kingma & Ba) on params with first/second moment
+ *   arrays m1, m2 (DEVICE fp32[P], zero before step 1), step >= 1.
+ * gf2_costmodel_predict: out[i] (DEVICE gf2_sched[N]) = table[argmin_s out_s]
+ *   with table a DEVICE gf2_sched[S] (the schedules the S outputs stand for).
+ */
+#define GF2_MLP_MAX_S 256
+
+typedef struct gf2_mlp {
+    float *params;
+    int32_t S;
+} gf2_mlp;
+
+int64_t gf2_mlp_param_count(int S);
+int gf2_mlp_init(gf2_ctx *ctx, gf2_mlp net, uint64_t seed, void *stream);
+int gf2_mlp_forward(gf2_ctx *ctx, gf2_mlp net, const float *feats, int64_t N, float *out,
+                    void *stream);
+size_t gf2_mlp_grad_workspace_bytes(int S, int64_t N);
+int gf2_mlp_grad(gf2_ctx *ctx, gf2_mlp net, const float *feats, const float *target,
+                 const float *mask, int64_t N, float inv_count, float *grad, void *ws,
+                 size_t ws_bytes, void *stream);
+int gf2_mlp_adam(gf2_ctx *ctx, gf2_mlp net, const float *grad, float *m1, float *m2, float lr,
+                 float beta1, float beta2, float eps, int step, void *stream);
+int gf2_costmodel_predict(gf2_ctx *ctx, gf2_mlp net, const float *feats, int64_t N,
+                          const gf2_sched *table, gf2_sched *out, void *stream);
+
 /* Workspace bytes gf2_addmul needs for C (m x n) += A (m x k) * B (k x n). */
 size_t gf2_addmul_workspace_bytes(int64_t m, int64_t k, int64_t n);
 

@@ -49,6 +49,10 @@ class BatchItem(ctypes.Structure):
                 ("stride", ctypes.c_int64), ("P", ctypes.c_void_p), ("Q", ctypes.c_void_p)]
 
 
+class MlpNet(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p), ("S", ctypes.c_int32)]
+
+
 class ProfStats(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
                 ("total_ops", ctypes.c_double)]
@@ -86,6 +90,32 @@ def _load():
     L.gf2_pls_batched_workspace_bytes.restype = sz
     L.gf2_pls_batched.argtypes = [vp, vp, i64, vp, vp, ctypes.POINTER(Sched), vp, sz, vp]
     L.gf2_pls_batched.restype = i32
+    L.gf2_sched_candidates.argtypes = [i64, i64, i32, ctypes.POINTER(Sched), i32]
+    L.gf2_sched_candidates.restype = i32
+    L.gf2_autotune_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(Sched), i32]
+    L.gf2_autotune_workspace_bytes.restype = sz
+    L.gf2_autotune.argtypes = [vp, Mat, Mat, ctypes.POINTER(Sched), i32, i32,
+                               ctypes.POINTER(ctypes.c_float), ctypes.POINTER(Sched), vp, sz, vp]
+    L.gf2_autotune.restype = i32
+    L.gf2_autotune_batched.argtypes = [vp, vp, vp, i64, vp, ctypes.POINTER(Sched), i32, i32,
+                                       ctypes.POINTER(ctypes.c_float), ctypes.POINTER(Sched), vp,
+                                       sz, vp]
+    L.gf2_autotune_batched.restype = i32
+    fp = ctypes.c_float
+    L.gf2_mlp_param_count.argtypes = [i32]
+    L.gf2_mlp_param_count.restype = i64
+    L.gf2_mlp_init.argtypes = [vp, MlpNet, ctypes.c_uint64, vp]
+    L.gf2_mlp_init.restype = i32
+    L.gf2_mlp_forward.argtypes = [vp, MlpNet, vp, i64, vp, vp]
+    L.gf2_mlp_forward.restype = i32
+    L.gf2_mlp_grad_workspace_bytes.argtypes = [i32, i64]
+    L.gf2_mlp_grad_workspace_bytes.restype = sz
+    L.gf2_mlp_grad.argtypes = [vp, MlpNet, vp, vp, vp, i64, fp, vp, vp, sz, vp]
+    L.gf2_mlp_grad.restype = i32
+    L.gf2_mlp_adam.argtypes = [vp, MlpNet, vp, vp, vp, fp, fp, fp, fp, i32, vp]
+    L.gf2_mlp_adam.restype = i32
+    L.gf2_costmodel_predict.argtypes = [vp, MlpNet, vp, i64, vp, vp, vp]
+    L.gf2_costmodel_predict.restype = i32
     L.gf2_addmul_workspace_bytes.argtypes = [i64, i64, i64]
     L.gf2_addmul_workspace_bytes.restype = sz
     L.gf2_addmul.argtypes = [vp, Mat, Mat, Mat, i32, vp, sz, vp]
@@ -259,6 +289,116 @@ class Batch:
     def pq(self, j: int):
         m, n = self.shapes[j]
         return (self.P[self.p_off[j]:self.p_off[j] + m], self.Q[self.q_off[j]:self.q_off[j] + n])
+
+
+def sched_candidates(m: int, n: int, batched: bool = False) -> list:
+    """The deduplicated candidate schedules for an m x n problem (host list)."""
+    L = get_lib()
+    cnt = L.gf2_sched_candidates(m, n, int(batched), None, 0)
+    if cnt < 0:
+        raise GF2Error(f"gf2 error {cnt}")
+    arr = (Sched * max(cnt, 1))()
+    L.gf2_sched_candidates(m, n, int(batched), arr, cnt)
+    return [Sched(*arr[i].astuple()) for i in range(cnt)]
+
+
+def autotune(A_trial: torch.Tensor, m: int, n: int, cands=None, reps: int = 2,
+             A_work: torch.Tensor | None = None, stream=None):
+    """Time every candidate schedule on A_trial (left unchanged); returns
+    (best Sched, list of fastest times in ms, one per candidate)."""
+    cands = sched_candidates(m, n) if cands is None else list(cands)
+    dev = A_trial.device
+    A_work = torch.empty_like(A_trial) if A_work is None else A_work
+    arr = (Sched * max(len(cands), 1))(*[Sched(*c.astuple()) for c in cands])
+    ms = (ctypes.c_float * max(len(cands), 1))()
+    best = Sched()
+    nb = int(get_lib().gf2_autotune_workspace_bytes(m, n, arr, len(cands)))
+    ws = workspace(nb, dev)
+    _check(get_lib().gf2_autotune(ctx(dev.index), _mat(A_trial, m, n), _mat(A_work, m, n), arr,
+                                  len(cands), reps, ms, ctypes.byref(best), ws.data_ptr(),
+                                  ws.numel(), _stream(stream)))
+    return Sched(*best.astuple()), [float(ms[i]) for i in range(len(cands))]
+
+
+def autotune_batched(trial: "Batch", work: "Batch", cands=None, reps: int = 2, stream=None):
+    """Time every candidate (k, tables) on the batch `trial` (restored into the
+    same-shaped batch `work` before each run); returns (best, times in ms)."""
+    cands = sched_candidates(64, 64, batched=True) if cands is None else list(cands)
+    arr = (Sched * max(len(cands), 1))(*[Sched(*c.astuple()) for c in cands])
+    ms = (ctypes.c_float * max(len(cands), 1))()
+    best = Sched()
+    _check(get_lib().gf2_autotune_batched(ctx(work.device.index), trial.items.data_ptr(),
+                                          work.items.data_ptr(), work.count, work.ranks.data_ptr(),
+                                          arr, len(cands), reps, ms, ctypes.byref(best),
+                                          work.ws.data_ptr(), work.ws.numel(), _stream(stream)))
+    return Sched(*best.astuple()), [float(ms[i]) for i in range(len(cands))]
+
+
+# ------------------------------------------------------------- cost model
+def mlp_param_count(S: int) -> int:
+    n = int(get_lib().gf2_mlp_param_count(S))
+    if n < 0:
+        raise GF2Error(f"gf2 error {n}")
+    return n
+
+
+def _f32(t: torch.Tensor, name: str):
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    return t.data_ptr()
+
+
+def mlp_init(params: torch.Tensor, S: int, seed: int, stream=None):
+    _check(get_lib().gf2_mlp_init(ctx(params.device.index), MlpNet(_f32(params, "params"), S),
+                                  seed, _stream(stream)))
+    return params
+
+
+def mlp_forward(params: torch.Tensor, S: int, feats: torch.Tensor, stream=None) -> torch.Tensor:
+    N = feats.shape[0]
+    out = torch.empty((N, S), dtype=torch.float32, device=params.device)
+    _check(get_lib().gf2_mlp_forward(ctx(params.device.index), MlpNet(_f32(params, "params"), S),
+                                     _f32(feats, "feats"), N, out.data_ptr(), _stream(stream)))
+    return out
+
+
+def mlp_grad(params: torch.Tensor, S: int, feats: torch.Tensor, target: torch.Tensor,
+             mask: torch.Tensor, inv_count: float, ws: torch.Tensor | None = None,
+             out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Gradient of the masked squared error (P values), then the loss."""
+    N = feats.shape[0]
+    dev = params.device
+    nb = int(get_lib().gf2_mlp_grad_workspace_bytes(S, N))
+    if ws is None or ws.numel() < nb:
+        ws = workspace(nb, dev)
+    out = torch.empty(mlp_param_count(S) + 1, dtype=torch.float32, device=dev) if out is None else out
+    _check(get_lib().gf2_mlp_grad(ctx(dev.index), MlpNet(_f32(params, "params"), S),
+                                  _f32(feats, "feats"), _f32(target, "target"), _f32(mask, "mask"),
+                                  N, float(inv_count), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                  _stream(stream)))
+    return out
+
+
+def mlp_adam(params: torch.Tensor, S: int, grad: torch.Tensor, m1: torch.Tensor, m2: torch.Tensor,
+             lr: float, step: int, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+             stream=None):
+    _check(get_lib().gf2_mlp_adam(ctx(params.device.index), MlpNet(_f32(params, "params"), S),
+                                  _f32(grad, "grad"), _f32(m1, "m1"), _f32(m2, "m2"), lr, beta1,
+                                  beta2, eps, step, _stream(stream)))
+
+
+def costmodel_predict(params: torch.Tensor, S: int, feats: torch.Tensor, table: torch.Tensor,
+                      stream=None) -> torch.Tensor:
+    """Per problem, the table row (k, tables, cutoff, schur) of the smallest
+    predicted log time; table is an int32 CUDA tensor (S, 4)."""
+    N = feats.shape[0]
+    if table.dtype != torch.int32 or tuple(table.shape) != (S, 4):
+        raise ValueError("table must be an int32 (S, 4) tensor")
+    out = torch.empty((max(N, 1), 4), dtype=torch.int32, device=params.device)
+    _check(get_lib().gf2_costmodel_predict(ctx(params.device.index),
+                                           MlpNet(_f32(params, "params"), S), _f32(feats, "feats"),
+                                           N, table.data_ptr(), out.data_ptr(), _stream(stream)))
+    return out[:N]
 
 
 def rref_workspace_bytes(m: int, n: int) -> int:

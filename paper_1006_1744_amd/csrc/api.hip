@@ -282,6 +282,10 @@ int gf2_ctx_create(gf2_ctx **out, int device) {
     c->device = device;
     c->cus = prop.multiProcessorCount;
     c->batch_bpc = batch_blocks_per_cu();
+    if (mlp_prepare() != hipSuccess) {
+        delete c;
+        return GF2_E_HIP;
+    }
     *out = c;
     return GF2_OK;
 }

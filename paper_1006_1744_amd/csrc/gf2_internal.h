@@ -140,6 +140,12 @@ hipError_t launch_rref_scatter(uint64_t *R, int64_t sr, int m, int n, const int3
 // Batched PLS (k_batch.hip): queue order, then one persistent launch of `grid`
 // blocks.  ws holds batch_ws_bytes(count) bytes.
 size_t batch_ws_bytes(int64_t count);
+hipError_t mlp_prepare();
+hipError_t launch_batch_copy(const gf2_batch_item *src, const gf2_batch_item *dst, int count,
+                             hipStream_t st);
+// Plain copy of an m x nw-word block between two strided matrices.
+hipError_t launch_copy_words(uint64_t *dst, int64_t sd, const uint64_t *src, int64_t ss, int64_t m,
+                             int64_t nw, hipStream_t st);
 int batch_blocks_per_cu();
 hipError_t launch_pls_batched(const gf2_batch_item *items, int count, int32_t *ranks,
                               const gf2_sched *per, gf2_sched def, int32_t *ws, int grid,

@@ -307,6 +307,28 @@ __global__ void batch_scatter_kernel(const gf2_batch_item *items, int count, int
     if (j < count) order[atomicAdd(&cursor[batch_bucket(items[j])], 1)] = j;
 }
 
+// Copy of every item's words from `src` to `dst` (same shapes), one block per
+// item: restores the inputs between timed runs.
+__global__ void batch_copy_kernel(const gf2_batch_item *src, const gf2_batch_item *dst, int count) {
+    for (int j = blockIdx.x; j < count; j += gridDim.x) {
+        const gf2_batch_item a = src[j], b = dst[j];
+        if (a.m != b.m || a.n != b.n || a.m <= 0 || a.n <= 0 || !a.words || !b.words) continue;
+        const int64_t nw = (a.n + 63) / 64;
+        for (int64_t e = threadIdx.x; e < a.m * nw; e += blockDim.x) {
+            const int64_t i = e / nw, w = e % nw;
+            b.words[i * b.stride + w] = a.words[i * a.stride + w];
+        }
+    }
+}
+
+hipError_t launch_batch_copy(const gf2_batch_item *src, const gf2_batch_item *dst, int count,
+                             hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const int grid = count < 4096 ? count : 4096;
+    hipLaunchKernelGGL(batch_copy_kernel, dim3(grid), dim3(256), 0, st, src, dst, count);
+    return hipGetLastError();
+}
+
 size_t batch_ws_bytes(int64_t count) {
     return (size_t)(2 * BT_BUCKETS + 64) * 4 + (size_t)count * 4;
 }

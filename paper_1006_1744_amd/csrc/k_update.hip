@@ -35,6 +35,27 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st)
     return hipGetLastError();
 }
 
+__global__ void copy_words_kernel(uint64_t *dst, int64_t sd, const uint64_t *src, int64_t ss,
+                                  int64_t m, int64_t nw) {
+    const int64_t total = m * nw;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / nw, w = e % nw;
+        dst[i * sd + w] = src[i * ss + w];
+    }
+}
+
+hipError_t launch_copy_words(uint64_t *dst, int64_t sd, const uint64_t *src, int64_t ss, int64_t m,
+                             int64_t nw, hipStream_t st) {
+    const int64_t total = m * nw;
+    if (total <= 0) return hipSuccess;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(copy_words_kernel, dim3((unsigned)blocks), dim3(256), 0, st, dst, sd, src, ss,
+                       m, nw);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ TRSM
 // X <- T^{-1} X on at most 64 rows: T^{-1} is formed by one wave (column-wise
 // substitution, tri_inverse64), then every output row is a combination of the

@@ -63,3 +63,29 @@ def test_null_context_rejected(lib):
     assert lib.gf2_pls(None, m, None, None, None, None, None, 0, None) == -1
     assert lib.gf2_rref(None, m, None, None, m, None, 0, None) == -1
     assert lib.gf2_addmul(None, m, m, m, 0, None, 0, None) == -1
+
+
+def test_sched_candidates_counts_and_validity():
+    import paper_1006_1744_amd as g
+    for m, n, batched, want in [(100, 100, False, 20), (300, 300, False, 60),
+                                (5000, 5000, False, 200), (64, 4096, False, 180),
+                                (64, 4097, False, 200), (3000, 3000, True, 20)]:
+        c = g.sched_candidates(m, n, batched)
+        assert len(c) == want
+        assert len({x.astuple() for x in c}) == want
+        assert all(g.get_lib().gf2_sched_valid(x) == 1 for x in c)
+        if not batched:
+            ncols = 64 * ((n + 63) // 64)
+            # one MMPF-only entry per (k, tables) when some cutoff covers the width
+            for k in range(4, 9):
+                for t in (1, 2, 4, 8):
+                    mm = [x for x in c if x.k == k and x.tables == t and x.cutoff >= ncols]
+                    assert len(mm) == (1 if ncols <= 4096 else 0)
+
+
+def test_mlp_param_counts():
+    import paper_1006_1744_amd as g
+    assert g.mlp_param_count(200) == 17480
+    assert g.mlp_param_count(20) == 5780
+    assert g.get_lib().gf2_mlp_param_count(0) < 0
+    assert g.get_lib().gf2_mlp_param_count(257) < 0
