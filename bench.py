@@ -12,6 +12,12 @@ operations 2*M*N*K per launch over its mean launch time, timed with HIP events
 on the launch stream during the timed steps, against the int8 dense MFMA peak.
 cpu_baseline: the CPU oracle (Gaussian PLS, Appendix A) timed on a smaller
 matrix of the same kind on this host.
+batched: the batched workload (4096 matrices, m and n log-uniform in
+[64, 2048], density in {0.5, 0.1, 0.01}, planted rank in [min/2, min],
+seed 7) decomposed by one persistent launch captured in a HIP graph, with
+the fixed default schedule and with the learned cost model's per-matrix
+schedules; matrices per second from HIP events around each graph replay
+(inputs restored from a pristine copy between replays, outside the timing).
 """
 from __future__ import annotations
 
@@ -25,6 +31,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 INT8_MFMA_PEAK_TOPS = 5000.0   # MI355X dense int8 matrix-core peak (TOP/s)
+
+# HBM traffic of the product kernel per launch (bytes), from two rocprofv3 PMC
+# passes over one step (FETCH_SIZE, then WRITE_SIZE), each scaled by what the
+# counter reads for a 1 GiB plain copy in the same run (x2 and x1).  Valid only
+# for the kernel source it was taken with (SHA-256 prefix); otherwise null.
+PMC_TRAFFIC = {"source": "paper_1006_1744_amd/csrc/k_mfma.hip", "sha256_16": "9ecfb312f77a751f",
+               "bytes_per_launch": (30.73 * 2 + 5.52) * 2**20,
+               "profile": "profiles/gemm_mfma2_traffic_65536.md"}
+
+
+def pmc_traffic():
+    import hashlib
+    path = os.path.join(ROOT, PMC_TRAFFIC["source"])
+    with open(path, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != PMC_TRAFFIC["sha256_16"]:
+            return None
+    return PMC_TRAFFIC["bytes_per_launch"]
 
 
 def classical_ops(m: int, n: int, r: int) -> float:
@@ -45,6 +68,59 @@ def cpu_baseline(n: int, seed: int) -> dict:
                       f"{dt:.2f} s, rank {r}"}
 
 
+def batched_leg(g, torch, reps: int) -> dict:
+    import synth
+    from paper_1006_1744_amd import costmodel as cmod
+    items = synth.batch_shapes(4096, 7)
+    host = [synth.batch_matrix(it) for it in items]
+    sizes = [a.size for a in host]
+    flat = torch.empty(sum(sizes), dtype=torch.int64, device="cuda")
+    mats, off = [], 0
+    for a in host:
+        v = flat[off:off + a.size].view(a.shape)
+        v.copy_(g.to_device(a))
+        mats.append(v)
+        off += a.size
+    pristine = flat.clone()
+    b = g.Batch(mats, [(it.m, it.n) for it in items])
+    cm = cmod.CostModel.load()
+    learned = cm.predict(cmod.mix_features(items))
+    out = {"workload": "4096 matrices, m,n log-uniform [64,2048], p in {0.5,0.1,0.01}, "
+                       "planted rank in [min/2,min], seed 7",
+           "graph": True}
+    for name, per in (("default", None), ("learned", learned)):
+        b.per_item = per
+        flat.copy_(pristine)
+        b.run()
+        torch.cuda.synchronize()
+        flat.copy_(pristine)
+        stream = torch.cuda.Stream()
+        graph = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=stream):
+            b.run()
+        ts = []
+        for _ in range(reps):
+            flat.copy_(pristine)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            graph.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = sorted(ts)[len(ts) // 2]
+        out[f"{name}_ms"] = round(ms, 3)
+        out[f"{name}_matrices_per_s"] = round(4096 / ms * 1e3, 1)
+        del graph
+    b.per_item = None
+    out["matrices_per_s"] = out["learned_matrices_per_s"]
+    out["unit"] = "matrices/s"
+    out["schedule"] = "learned per matrix (cost model), default for comparison"
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,10 +128,14 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--cpu-n", type=int, default=24576)
+    ap.add_argument("--cpu-n", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-rref", action="store_true")
     ap.add_argument("--sched", type=str, default="")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the run, one plain device copy of this many MiB (a known-size "
+                         "dispatch that calibrates hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path "
@@ -101,8 +181,10 @@ def main() -> int:
         step(i)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    launches = g.prof_launches()
     prof = g.prof_read()
     g.prof_disable()
+    alg_bytes = sum((M * K + N * K + 2 * M * N) / 8 for _, M, N, K in launches)
     r = int(rank.item())
     ms = (t1 - t0) * 1e3 / args.steps
     ops = classical_ops(m, n, r)
@@ -112,7 +194,8 @@ def main() -> int:
     roofline = {"bound": "mfma", "kernel": "gemm_mfma_kernel (int8 MFMA Schur product)",
                 "achieved": round(achieved, 1), "peak": INT8_MFMA_PEAK_TOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / INT8_MFMA_PEAK_TOPS, 4),
-                "traffic": None,
+                "traffic": pmc_traffic(),
+                "alg_bytes_per_launch": round(alg_bytes / max(len(launches), 1)),
                 "launches_per_step": prof["launches"] // max(args.steps, 1),
                 "mean_launch_us": round(prof["ms"] * 1e3 / max(prof["launches"], 1), 2),
                 "kernel_share_of_step": round(prof["ms"] / args.steps / ms, 3)}
@@ -125,8 +208,19 @@ def main() -> int:
                       "m": m, "n": n, "rank": r,
                       "schedule": str(s) if s is not None else str(g.default_sched())},
            "roofline": roofline}
+    del copies
+    torch.cuda.empty_cache()
+    if not args.no_batch:
+        out["batched"] = batched_leg(g, torch, max(3, args.steps))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.seed)
+    if args.calib_copy_mib > 0:
+        x = torch.ones(args.calib_copy_mib << 17, dtype=torch.int64, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = x.numel() * 8
     print(json.dumps(out), flush=True)
     return 0
 
