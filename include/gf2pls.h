@@ -103,6 +103,19 @@ size_t gf2_pls_workspace_bytes(int64_t m, int64_t n, const gf2_sched *s);
 int gf2_pls(gf2_ctx *ctx, gf2_mat A, int32_t *P, int32_t *Q, int32_t *rank,
             const gf2_sched *s, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * Explicit factors from a gf2_pls result (Section 2's A = P L S; in-place layout
+ * of Sections 4-5).  A_pls, Q, rank are gf2_pls outputs (device); A_pls is only
+ * read.  With rmax = min(m, n):
+ *  L_out  m x rmax (device): row i has the stored L bits of columns < min(i, r),
+ *         a one at column i when i < r, zeros elsewhere (columns >= r are zero).
+ *  S_out  rmax x n (device): row i < r has a one at Q[i], zeros left of it and the
+ *         stored S bits right of it; rows >= r are not written.
+ * Then A = P L S with L truncated to r columns and S to r rows.
+ */
+int gf2_pls_unpack(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int32_t *rank,
+                   gf2_mat L_out, gf2_mat S_out, void *stream);
+
 /* Workspace bytes gf2_rref needs. */
 size_t gf2_rref_workspace_bytes(int64_t m, int64_t n);
 

@@ -82,6 +82,8 @@ def _load():
     L.gf2_pls_workspace_bytes.restype = sz
     L.gf2_pls.argtypes = [vp, Mat, vp, vp, vp, ctypes.POINTER(Sched), vp, sz, vp]
     L.gf2_pls.restype = i32
+    L.gf2_pls_unpack.argtypes = [vp, Mat, vp, vp, Mat, Mat, vp]
+    L.gf2_pls_unpack.restype = i32
     L.gf2_rref_workspace_bytes.argtypes = [i64, i64]
     L.gf2_rref_workspace_bytes.restype = sz
     L.gf2_rref.argtypes = [vp, Mat, vp, vp, Mat, vp, sz, vp]
@@ -399,6 +401,19 @@ def costmodel_predict(params: torch.Tensor, S: int, feats: torch.Tensor, table: 
                                            MlpNet(_f32(params, "params"), S), _f32(feats, "feats"),
                                            N, table.data_ptr(), out.data_ptr(), _stream(stream)))
     return out[:N]
+
+
+def pls_unpack(A_pls: torch.Tensor, m: int, n: int, Q: torch.Tensor, rank: torch.Tensor,
+               stream=None):
+    """Explicit (L, S) from a PLS result: L m x min(m,n), S min(m,n) x n (int64 CUDA
+    tensors, packed rows); only the first rank columns of L and rows of S count."""
+    dev = A_pls.device
+    rmax = min(m, n)
+    L = torch.zeros((max(m, 1), max((rmax + 63) // 64, 1)), dtype=torch.int64, device=dev)[:m]
+    S = torch.zeros((max(rmax, 1), max((n + 63) // 64, 1)), dtype=torch.int64, device=dev)[:rmax]
+    _check(get_lib().gf2_pls_unpack(ctx(dev.index), _mat(A_pls, m, n), Q.data_ptr(), rank.data_ptr(),
+                                    _mat(L, m, rmax), _mat(S, rmax, n), _stream(stream)))
+    return L, S
 
 
 def rref_workspace_bytes(m: int, n: int) -> int:

@@ -420,6 +420,24 @@ int gf2_pls(gf2_ctx *ctx, gf2_mat A, int32_t *P, int32_t *Q, int32_t *rank, cons
     return d.err == hipSuccess ? GF2_OK : GF2_E_HIP;
 }
 
+int gf2_pls_unpack(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int32_t *rank,
+                   gf2_mat L_out, gf2_mat S_out, void *stream) {
+    if (!ctx || !Q || !rank) return GF2_E_ARG;
+    int rc = check_mat(A_pls);
+    if (rc != GF2_OK) return rc;
+    const int64_t rmax = std::min(A_pls.m, A_pls.n);
+    if (L_out.m != A_pls.m || L_out.n != rmax || S_out.m != rmax || S_out.n != A_pls.n)
+        return GF2_E_ARG;
+    if ((rc = check_mat(L_out)) != GF2_OK || (rc = check_mat(S_out)) != GF2_OK) return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess) return GF2_E_HIP;
+    const int lwords = (int)((rmax + 63) / 64), swords = (int)((A_pls.n + 63) / 64);
+    const int64_t maxw = A_pls.m * lwords + rmax * swords;
+    hipError_t e = launch_unpack(A_pls.words, A_pls.stride, (int)A_pls.m, (int)A_pls.n, Q, rank,
+                                 L_out.words, L_out.stride, lwords, S_out.words, S_out.stride, swords,
+                                 maxw, (hipStream_t)stream);
+    return e == hipSuccess ? GF2_OK : GF2_E_HIP;
+}
+
 size_t gf2_pls_batched_workspace_bytes(int64_t count) {
     if (count < 0) return 0;
     return align_up(batch_ws_bytes(count));

@@ -141,6 +141,9 @@ hipError_t launch_rref_scatter(uint64_t *R, int64_t sr, int m, int n, const int3
 // blocks.  ws holds batch_ws_bytes(count) bytes.
 size_t batch_ws_bytes(int64_t count);
 hipError_t mlp_prepare();
+hipError_t launch_unpack(const uint64_t *A, int64_t sa, int m, int n, const int32_t *Q,
+                         const int32_t *rank, uint64_t *L, int64_t sl, int lwords, uint64_t *S,
+                         int64_t ss, int swords, int64_t max_words, hipStream_t st);
 hipError_t launch_batch_copy(const gf2_batch_item *src, const gf2_batch_item *dst, int count,
                              hipStream_t st);
 // Plain copy of an m x nw-word block between two strided matrices.

@@ -198,4 +198,55 @@ hipError_t launch_rref_scatter(uint64_t *R, int64_t sr, int m, int n, const int3
     return hipGetLastError();
 }
 
+// Explicit factors from the compressed in-place result: L (m x r, unit lower
+// trapezoidal: row i holds the stored bits of columns < min(i, r) and a one at
+// column i when i < r) and S (r x n: one at Q[i], zeros left of it, the stored
+// bits right of it).  One thread per output word.
+__global__ void unpack_kernel(const uint64_t *A, int64_t sa, int m, int n, const int32_t *Q,
+                              const int32_t *rank, uint64_t *L, int64_t sl, int lwords, uint64_t *S,
+                              int64_t ss, int swords) {
+    const int r = *rank;
+    const int64_t totL = (int64_t)m * lwords, totS = (int64_t)r * swords;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < totL + totS;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        if (e < totL) {
+            const int i = (int)(e / lwords), w = (int)(e % lwords);
+            const int k = min(i, r);   // stored L bits: columns [0, k)
+            uint64_t v = 0;
+            if (64 * w < k) {
+                v = A[(int64_t)i * sa + w];
+                const int hi = k - 64 * w;
+                if (hi < 64) v &= (1ull << hi) - 1;
+            }
+            if (i < r && (i >> 6) == w) v |= 1ull << (i & 63);
+            if (64 * w >= r) v = 0;
+            else if (r - 64 * w < 64) v &= (1ull << (r - 64 * w)) - 1;
+            L[(int64_t)i * sl + w] = v;
+        } else {
+            const int64_t f = e - totL;
+            const int i = (int)(f / swords), w = (int)(f % swords);
+            const int q = Q[i];
+            uint64_t v = A[(int64_t)i * sa + w];
+            // keep columns > q, set column q, clear the rest
+            const int lo = q + 1 - 64 * w;   // first kept bit in this word
+            if (lo >= 64) v = 0;
+            else if (lo > 0) v &= ~0ull << lo;
+            if ((q >> 6) == w) v |= 1ull << (q & 63);
+            if (64 * w + 64 > n) v &= n - 64 * w >= 64 ? ~0ull : ((1ull << (n - 64 * w)) - 1);
+            S[(int64_t)i * ss + w] = v;
+        }
+    }
+}
+
+hipError_t launch_unpack(const uint64_t *A, int64_t sa, int m, int n, const int32_t *Q,
+                         const int32_t *rank, uint64_t *L, int64_t sl, int lwords, uint64_t *S,
+                         int64_t ss, int swords, int64_t max_words, hipStream_t st) {
+    if (max_words <= 0) return hipSuccess;
+    int64_t blocks = (max_words + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(unpack_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A, sa, m, n, Q, rank,
+                       L, sl, lwords, S, ss, swords);
+    return hipGetLastError();
+}
+
 }  // namespace gf2

@@ -176,3 +176,28 @@ def test_rref_4096():
     dR = g.rref(dAp, n, n, dQ, drank)
     torch.cuda.synchronize()
     assert gr == r and np.array_equal(g.to_host(dR), R)
+
+
+# ---------------------------------------------------------------- unpack
+@pytest.mark.parametrize("m,n,kind", [(1, 1, "half"), (300, 257, "half"), (257, 300, "half"),
+                                      (500, 700, "planted"), (700, 130, "sparse"), (200, 200, "zero")])
+def test_pls_unpack(m, n, kind):
+    if kind == "half":
+        A = synth.random_half(m, n, 3 * m + n)
+    elif kind == "planted":
+        A = synth.planted(m, n, 321, 4, p=0.5)
+    elif kind == "sparse":
+        A = synth.random_bernoulli(m, n, 0.01, 6)
+    else:
+        A = synth.empty(m, n)
+    say(f"[unpack] {kind} m={m} n={n}")
+    r, P, Q, Ap = oracle.pls(A, m, n)
+    L0, S0 = oracle.unpack_LS(Ap, m, n, r, Q)
+    gr, gP, gQ, gAp, dAp, dQ, drank = gpu_pls(A, m, n)
+    dL, dS = g.pls_unpack(dAp, m, n, dQ, drank)
+    torch.cuda.synchronize()
+    rmax = min(m, n)
+    L = oracle.unpack_bits(g.to_host(dL), rmax)
+    S = oracle.unpack_bits(g.to_host(dS), n)
+    assert np.array_equal(L[:, :r], L0) and not L[:, r:].any()
+    assert np.array_equal(S[:r], S0)
