@@ -145,6 +145,7 @@ struct PlsDriver {
     const uint64_t *linv = nullptr;   // L^{-1} rows inside the panel record
     uint64_t *Bt = nullptr;
     uint64_t *Bbuf = nullptr;         // staged pivot rows, 64 x bstride words
+    uint64_t *linv_store = nullptr;   // per panel: L^{-1} of its pivot block (64 words)
     int64_t bstride = 0;
     int cus = 256;
     size_t bt_words = 0;   // capacity (launch) or requirement (dry)
@@ -174,7 +175,8 @@ struct PlsDriver {
         if (sz <= trsm_block_max_rows()) {
             if (!dry)
                 chk(launch_trsm_block(A, stride, A, stride, m, row_range(ib, ie, a, sz),
-                                      lw0 + a / 64, w_lo, w_hi, rk, 1, (sz + 63) / 64, st));
+                                      lw0 + a / 64, w_lo, w_hi, rk, 1, (sz + 63) / 64, linv_store,
+                                      st));
             return;
         }
         const int h = (sz / 64 / 2) * 64;
@@ -194,7 +196,7 @@ struct PlsDriver {
             const bool upd = p + 1 < nwd;
             if (!dry)
                 chk(launch_leaf(A, stride, m, n, wc, rk, wc, P, Q, info, upd ? Bbuf : nullptr,
-                                bstride, wc + 1, wb + nwd, st));
+                                bstride, wc + 1, wb + nwd, linv_store, st));
             if (upd && !dry)
                 chk(launch_table_update(A, stride, m, wc, rk, wc, wc + 1, wb + nwd, s.k, s.tables,
                                         linv, Bbuf, bstride, cus, st));
@@ -227,7 +229,7 @@ struct PlsDriver {
 };
 
 struct PlsLayout {
-    size_t rk_off, info_off, bt_off, bb_off, total;
+    size_t rk_off, info_off, bt_off, bb_off, linv_off, total;
     size_t bt_words;
     int64_t bstride;
 };
@@ -252,6 +254,8 @@ PlsLayout pls_layout(int64_t m, int64_t n, const gf2_sched &s) {
     L.bb_off = off;
     L.bstride = std::max<int64_t>(d.bstride, 1);
     off = align_up(off + (size_t)64 * L.bstride * 8);
+    L.linv_off = off;
+    off = align_up(off + (size_t)(d.nb + 1) * 64 * 8);
     L.total = off;
     return L;
 }
@@ -410,6 +414,7 @@ int gf2_pls(gf2_ctx *ctx, gf2_mat A, int32_t *P, int32_t *Q, int32_t *rank, cons
     d.Bbuf = (uint64_t *)(base + L.bb_off);
     d.bstride = L.bstride;
     d.linv = (const uint64_t *)(base + L.info_off + panel_info_linv_offset());
+    d.linv_store = (uint64_t *)(base + L.linv_off);
     d.cus = ctx->cus;
     d.P = P;
     d.Q = Q;
@@ -509,7 +514,7 @@ struct UpperSolve {
         if (a >= r || sz <= 0) return;
         if (sz <= trsm_block_max_rows()) {
             chk(launch_trsm_block(X, sx, U, su, r, row_range(-1, -1, a, sz), a / 64, 0, nwx, rr, 0,
-                                  (sz + 63) / 64, st));
+                                  (sz + 63) / 64, nullptr, st));
             return;
         }
         const int h = (sz / 64 / 2) * 64;

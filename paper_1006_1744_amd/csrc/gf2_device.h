@@ -42,25 +42,49 @@ __device__ inline uint64_t transpose64(uint64_t v, int lane) {
 
 // Inverse of a 64 x 64 unit triangular matrix T given by the rows in LDS `rows`
 // (only the strictly lower part, bits < i of row i, is read when lower != 0;
-// only the strictly upper part otherwise).  Lane j solves T x = e_j by
-// substitution, one row per step, so every step is a parity of an AND; the
-// result is returned as rows (lane i = row i of T^{-1}).
-__device__ inline uint64_t tri_inverse64(const uint64_t *rows, int lane, bool lower) {
-    uint64_t x = 0;
+// only the strictly upper part otherwise).  Lane j holds row j, and solves
+// T x = e_j column by column: for each column s (upward for lower, downward for
+// upper), if x has bit s set it adds column s of T (one ballot over the rows).
+// x is then column j of T^{-1}; the result is returned as rows (lane i = row i
+// of T^{-1}) by one transpose.
+__device__ inline uint64_t tri_inverse64_row(uint64_t row, int lane, bool lower) {
+    uint64_t x = 1ull << lane;
     if (lower) {
-        for (int i = 0; i < 64; i++) {
-            const uint64_t li = rows[i] & ((1ull << i) - 1);
-            uint64_t b = (uint64_t)((__popcll(li & x) & 1) ^ (i == lane));
-            x |= b << i;
+        for (int s = 0; s < 63; s++) {
+            const uint64_t col = __ballot(lane > s && ((row >> s) & 1ull));
+            if ((x >> s) & 1ull) x ^= col;
         }
     } else {
-        for (int i = 63; i >= 0; i--) {
-            const uint64_t ui = i == 63 ? 0ull : (rows[i] & (~0ull << (i + 1)));
-            uint64_t b = (uint64_t)((__popcll(ui & x) & 1) ^ (i == lane));
-            x |= b << i;
+        for (int s = 63; s > 0; s--) {
+            const uint64_t col = __ballot(lane < s && ((row >> s) & 1ull));
+            if ((x >> s) & 1ull) x ^= col;
         }
     }
     return transpose64(x, lane);
+}
+
+__device__ inline uint64_t tri_inverse64(const uint64_t *rows, int lane, bool lower) {
+    return tri_inverse64_row(rows[lane], lane, lower);
+}
+
+// Tables of all 16 combinations of each 4 consecutive rows, built directly
+// (each entry the XOR of at most 4 rows, one barrier at the end): for group g,
+// T[(g * 16 + e) * TW + w] = XOR of rows 4g + u with bit u of e set (rows past
+// nrows read as zero).  rows: LDS [>= 4*ng][TW].  All threads must call it.
+template <int TW>
+__device__ inline void build_tables_k4(const uint64_t *rows, int nrows, int ng, uint64_t *T,
+                                       int tid, int nthr) {
+    for (int e = tid; e < ng * 16 * TW; e += nthr) {
+        const int w = e % TW, idx = (e / TW) & 15, g = e / (16 * TW);
+        uint64_t v = 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int row = 4 * g + u;
+            if (((idx >> u) & 1) && row < nrows) v ^= rows[row * TW + w];
+        }
+        T[e] = v;
+    }
+    __syncthreads();
 }
 
 // Tables of all combinations of groups of k consecutive rows: for group g,

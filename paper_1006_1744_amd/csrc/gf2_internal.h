@@ -59,7 +59,7 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st)
 // Bbuf (row t at Bbuf + t * bstride) when Bbuf is non-null.
 hipError_t launch_leaf(uint64_t *A, int64_t stride, int m, int n, int wc, int32_t *rk, int b,
                        int32_t *P, int32_t *Q, int32_t *info, uint64_t *Bbuf, int64_t bstride,
-                       int bw_lo, int bw_hi, hipStream_t st);
+                       int bw_lo, int bw_hi, uint64_t *linv_store, hipStream_t st);
 size_t panel_info_bytes();
 size_t panel_info_linv_offset();
 
@@ -76,7 +76,7 @@ hipError_t launch_trsm_base(uint64_t *A, int64_t stride, const uint64_t *Lm, int
 // at word lw0 (diagonal block b at word lw0 + b).  lower = 0: unit upper.
 hipError_t launch_trsm_block(uint64_t *A, int64_t stride, const uint64_t *Lm, int64_t sl, int m,
                              RowRange rows, int lw0, int w_lo, int w_hi, const int32_t *rk,
-                             int lower, int nbmax, hipStream_t st);
+                             int lower, int nbmax, const uint64_t *linv_store, hipStream_t st);
 int trsm_block_max_rows();
 
 // Table-driven update after a panel (Section 4.1: MakeTable1 / AddRowsFromTable)

@@ -7,11 +7,14 @@ namespace gf2 {
 
 __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
     uint64_t *A, int64_t stride, int m, int n, int wc, int32_t *rk, int b, int32_t *P,
-    int32_t *Q, PanelInfo *info) {
+    int32_t *Q, PanelInfo *info, uint64_t *linv_store) {
     __shared__ SearchLds S;
     const int R = rk[b];
     const int r = panel_search(A, stride, m, n, wc, R, P, Q, info, S);
     if (threadIdx.x == 0) rk[b + 1] = R + r;
+    // the panel's L^{-1}, kept per panel for the triangular solves above it
+    if (linv_store && threadIdx.x < 64)
+        linv_store[(int64_t)b * 64 + threadIdx.x] = info->linv[threadIdx.x];
 }
 
 // Final pass over the panel (blocks [0, nfin)) and the other word columns of
@@ -117,10 +120,11 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
 
 hipError_t launch_leaf(uint64_t *A, int64_t stride, int m, int n, int wc, int32_t *rk, int b,
                        int32_t *P, int32_t *Q, int32_t *infobuf, uint64_t *Bbuf,
-                       int64_t bstride, int bw_lo, int bw_hi, hipStream_t st) {
+                       int64_t bstride, int bw_lo, int bw_hi, uint64_t *linv_store,
+                       hipStream_t st) {
     PanelInfo *info = reinterpret_cast<PanelInfo *>(infobuf);
     hipLaunchKernelGGL(leaf_search_kernel, dim3(1), dim3(LEAF_THREADS), 0, st, A, stride, m, n,
-                       wc, rk, b, P, Q, info);
+                       wc, rk, b, P, Q, info, linv_store);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int nwords = (n + 63) / 64;

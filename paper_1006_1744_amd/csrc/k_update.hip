@@ -92,7 +92,7 @@ __global__ __launch_bounds__(TRSM_THREADS) void trsm_base_kernel(
     }
     __syncthreads();
     if (tid < 64) sInv[lane] = tri_inverse64(sL, lane, lower != 0);
-    build_group_tables(sB, nr, TRSM_K, TRSM_NG, sT, TRSM_TW, tid, TRSM_THREADS);
+    build_tables_k4<TRSM_TW>(sB, nr, TRSM_NG, sT, tid, TRSM_THREADS);
     for (int e = tid; e < nr * TRSM_TW; e += TRSM_THREADS) {
         const int i = e / TRSM_TW, w = e % TRSM_TW;
         const uint64_t c = sInv[i];
@@ -116,27 +116,33 @@ hipError_t launch_trsm_base(uint64_t *A, int64_t stride, const uint64_t *Lm, int
 
 // ------------------------------------------------------- blocked TRSM
 // X <- T^{-1} X for up to TB_NB blocks of 64 rows in one launch (unit lower or
-// unit upper T, its rows in Lm).  Each block's own 64 x 64 inverse is formed by
-// one wave; the blocks are then solved in order (forward for lower, backward
-// for upper): a block first adds, for every block already solved, one table row
-// per group of 4 multipliers (AddRowsFromTable on the tables of that block's
-// solution, MakeTable with k = 4), then is multiplied by its diagonal inverse
-// with the same kind of tables.  One launch replaces the bottom levels of the
-// recursive solve (Section 5 reduces it to products), whose products would be
-// too small to fill the device.
-constexpr int TB_THREADS = 256;
+// unit upper T, its rows in Lm), one thread per row, two words of X per block.
+// Each diagonal block's 64 x 64 inverse is formed by one wave (or, for a lower
+// block that is exactly the 64 pivots of a full-rank panel, read from the
+// inverse the panel search stored).  The blocks are then solved in order
+// (forward for lower, backward for upper), right-looking: block b is
+// multiplied by its diagonal inverse (tables of all 16 combinations of each 4
+// of its rows, MakeTable with k = 4, and one table row per group of 4
+// multipliers, AddRowsFromTable), the solved rows are tabulated the same way,
+// and every row of the blocks still to come adds their combination selected
+// by its L word of block column b.  A thread loads its row's L words once, in
+// solve order, so no step waits on memory.  One launch replaces the bottom
+// levels of the recursive solve (Section 5 reduces it to products), whose
+// products would be too small to fill the device.
+constexpr int TB_THREADS = 1024;
 constexpr int TB_NB = 16;
 constexpr int TB_TW = 2;
 
+struct alignas(16) Word2 {
+    uint64_t a, b;
+};
+
 __global__ __launch_bounds__(TB_THREADS) void trsm_block_kernel(
     uint64_t *A, int64_t stride, const uint64_t *Lm, int64_t sl, int m, RowRange rows, int lw0,
-    int w_lo, int w_hi, const int32_t *rk, int lower, int nbmax) {
-    __shared__ uint64_t sX[TB_NB * 64 * TB_TW];
-    __shared__ uint64_t sT[TB_NB * 256 * TB_TW];
-    __shared__ uint64_t sC[256 * TB_TW];
+    int w_lo, int w_hi, const int32_t *rk, int lower, int nbmax, const uint64_t *linv_store) {
+    __shared__ Word2 sX[TB_NB * 64];
+    __shared__ Word2 sT[256];
     __shared__ uint64_t sInv[TB_NB * 64];
-    __shared__ uint64_t sDiag[TB_NB * 64];
-    __shared__ uint64_t sL[64 * TB_NB];      // L words of the current block's rows
     int r0, r1;
     eval_range(rk, m, rows, r0, r1);
     const int nr = min(r1 - r0, nbmax * 64);
@@ -146,74 +152,74 @@ __global__ __launch_bounds__(TB_THREADS) void trsm_block_kernel(
     const int w0 = w_lo + blockIdx.x * TB_TW;
     const int tw_n = min(TB_TW, w_hi - w0);
     if (tw_n <= 0) return;
-    for (int e = tid; e < nb * 64 * TB_TW; e += TB_THREADS) {
-        const int r = e / TB_TW, w = e % TB_TW;
-        sX[e] = (r < nr && w < tw_n) ? A[(int64_t)(r0 + r) * stride + w0 + w] : 0ull;
+    const int row = tid, rb = row >> 6;
+    const bool have = row < nr;
+    // every load of this thread at once: its X words, its diagonal word and its
+    // L words in solve order (step s uses block column lower ? s : nb - 1 - s)
+    Word2 x = {0ull, 0ull};
+    uint64_t dg = 0, lw[TB_NB];
+    if (have) {
+        const uint64_t *pa = A + (int64_t)(r0 + row) * stride + w0;
+        x.a = pa[0];
+        if (tw_n > 1) x.b = pa[1];
+        const uint64_t *pl = Lm + (int64_t)(r0 + row) * sl + lw0;
+        const int valid = nr - 64 * rb;
+        dg = pl[rb] & (valid >= 64 ? ~0ull : ((1ull << valid) - 1));
     }
-    // every diagonal block's rows at once, then one wave per block inverts
-    for (int e = tid; e < nb * 64; e += TB_THREADS) {
-        const int b = e >> 6, row = e;
-        const int valid = nr - 64 * b;
-        const uint64_t keep = valid >= 64 ? ~0ull : ((1ull << valid) - 1);
-        sDiag[e] = row < nr ? (Lm[(int64_t)(r0 + row) * sl + lw0 + b] & keep) : 0ull;
-    }
-    // L words (all TB_NB word columns) of one block's rows, TB_LPT per thread
-    constexpr int TB_LPT = 64 * TB_NB / TB_THREADS;
-    uint64_t pre[TB_LPT];
-    auto load_l = [&](int b) {
 #pragma unroll
-        for (int j = 0; j < TB_LPT; j++) {
-            const int e = tid + TB_THREADS * j;
-            const int row = 64 * b + e / TB_NB, a = e % TB_NB;
-            pre[j] = (row < nr && a < nb && a != b) ? Lm[(int64_t)(r0 + row) * sl + lw0 + a] : 0ull;
-        }
-    };
-    load_l(lower ? 0 : nb - 1);
+    for (int st = 0; st < TB_NB; st++) {
+        const int c = lower ? st : nb - 1 - st;
+        const bool later = lower ? rb > c : rb < c;
+        lw[st] = (have && st < nb && later) ? Lm[(int64_t)(r0 + row) * sl + lw0 + c] : 0ull;
+    }
+    sX[row] = x;
+    if (wave < nb) {
+        const int P = lw0 + wave;   // the panel whose pivots these rows would be
+        const bool stored = lower && linv_store && rk[P] == 64 * P && rk[P + 1] == 64 * P + 64 &&
+                            r0 + 64 * wave == 64 * P;
+        sInv[row] = stored ? linv_store[(int64_t)P * 64 + lane] : tri_inverse64_row(dg, lane, lower != 0);
+    }
     __syncthreads();
-    for (int b = wave; b < nb; b += TB_THREADS / 64)
-        sInv[64 * b + lane] = tri_inverse64(sDiag + 64 * b, lane, lower != 0);
-    __syncthreads();
-    for (int bi = 0; bi < nb; bi++) {
-        const int b = lower ? bi : nb - 1 - bi;
+#pragma unroll
+    for (int st = 0; st < TB_NB; st++) {
+        if (st >= nb) break;
+        const int b = lower ? st : nb - 1 - st;
         const int bn = min(64, nr - 64 * b);
+        // diagonal: X_b <- Inv_bb X_b
+        build_tables_k4<TB_TW>(&sX[64 * b].a, bn, 16, &sT[0].a, tid, TB_THREADS);
+        if (rb == b && have) {
+            const uint64_t c = sInv[row];
+            Word2 y = {0ull, 0ull};
 #pragma unroll
-        for (int j = 0; j < TB_LPT; j++) sL[tid + TB_THREADS * j] = pre[j];
-        __syncthreads();
-        if (bi + 1 < nb) load_l(lower ? b + 1 : b - 1);   // in flight during this block
-        if (bi > 0) {
-            const int a_lo = lower ? 0 : b + 1, a_hi = lower ? b : nb;
-            for (int e = tid; e < bn * TB_TW; e += TB_THREADS) {
-                const int i = e / TB_TW, w = e % TB_TW;
-                const int row = 64 * b + i;
-                uint64_t x = sX[row * TB_TW + w];
-                for (int a = a_lo; a < a_hi; a++) {
-                    const uint64_t lv = sL[i * TB_NB + a];
-                    const uint64_t *T = sT + (size_t)a * 256 * TB_TW;
-#pragma unroll
-                    for (int g = 0; g < 16; g++)
-                        x ^= T[((g << 4) + (int)((lv >> (4 * g)) & 15)) * TB_TW + w];
-                }
-                sX[row * TB_TW + w] = x;
+            for (int g = 0; g < 16; g++) {
+                const Word2 t = sT[(g << 4) + (int)((c >> (4 * g)) & 15)];
+                y.a ^= t.a;
+                y.b ^= t.b;
             }
-            __syncthreads();
-        }
-        build_group_tables(sX + (size_t)64 * b * TB_TW, bn, 4, 16, sC, TB_TW, tid, TB_THREADS);
-        for (int e = tid; e < bn * TB_TW; e += TB_THREADS) {
-            const int i = e / TB_TW, w = e % TB_TW;
-            const uint64_t c = sInv[64 * b + i];
-            uint64_t x = 0;
-#pragma unroll
-            for (int g = 0; g < 16; g++) x ^= sC[((g << 4) + (int)((c >> (4 * g)) & 15)) * TB_TW + w];
-            sX[(64 * b + i) * TB_TW + w] = x;
+            sX[row] = y;
         }
         __syncthreads();
-        if (bi + 1 < nb)
-            build_group_tables(sX + (size_t)64 * b * TB_TW, bn, 4, 16, sT + (size_t)b * 256 * TB_TW,
-                               TB_TW, tid, TB_THREADS);
+        if (st + 1 == nb) break;
+        // the blocks still to come: x_r += L[r][b] X_b
+        build_tables_k4<TB_TW>(&sX[64 * b].a, bn, 16, &sT[0].a, tid, TB_THREADS);
+        const uint64_t lv = lw[st];
+        if (lv) {
+            Word2 y = sX[row];
+#pragma unroll
+            for (int g = 0; g < 16; g++) {
+                const Word2 t = sT[(g << 4) + (int)((lv >> (4 * g)) & 15)];
+                y.a ^= t.a;
+                y.b ^= t.b;
+            }
+            sX[row] = y;
+        }
+        __syncthreads();
     }
-    for (int e = tid; e < nr * TB_TW; e += TB_THREADS) {
-        const int r = e / TB_TW, w = e % TB_TW;
-        if (w < tw_n) A[(int64_t)(r0 + r) * stride + w0 + w] = sX[e];
+    if (have) {
+        uint64_t *pa = A + (int64_t)(r0 + row) * stride + w0;
+        const Word2 y = sX[row];
+        pa[0] = y.a;
+        if (tw_n > 1) pa[1] = y.b;
     }
 }
 
@@ -221,12 +227,12 @@ int trsm_block_max_rows() { return TB_NB * 64; }
 
 hipError_t launch_trsm_block(uint64_t *A, int64_t stride, const uint64_t *Lm, int64_t sl, int m,
                              RowRange rows, int lw0, int w_lo, int w_hi, const int32_t *rk,
-                             int lower, int nbmax, hipStream_t st) {
+                             int lower, int nbmax, const uint64_t *linv_store, hipStream_t st) {
     if (w_hi <= w_lo) return hipSuccess;
     if (nbmax > TB_NB) nbmax = TB_NB;
     int nb = (w_hi - w_lo + TB_TW - 1) / TB_TW;
     hipLaunchKernelGGL(trsm_block_kernel, dim3(nb), dim3(TB_THREADS), 0, st, A, stride, Lm, sl, m,
-                       rows, lw0, w_lo, w_hi, rk, lower, nbmax);
+                       rows, lw0, w_lo, w_hi, rk, lower, nbmax, linv_store);
     return hipGetLastError();
 }
 
