@@ -172,45 +172,54 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
             uint64_t c0 = transpose64(x0, lane), c1 = transpose64(x1, lane);
             TR();
             int fer = -1;   // lane j: window entry of the pivot of column j (this epoch)
-            int tt = t, cc = c, brk = 0;
-            while (true) {
-                cc = __builtin_amdgcn_readfirstlane(cc);
-                tt = __builtin_amdgcn_readfirstlane(tt);
-                if (cc >= nc || tt >= mrem) break;
+            // loop state kept in scalar registers: column, pivot count, candidates
+            int cc = __builtin_amdgcn_readfirstlane(c);
+            int tt = __builtin_amdgcn_readfirstlane(t);
+            const int tsu = __builtin_amdgcn_readfirstlane(ts);
+            int brk = 0;
+            while (cc < nc && tt < mrem) {
                 const uint64_t b0 = readlane64(c0, cc) & m0;
                 const uint64_t b1 = readlane64(c1, cc) & m1;
-                if ((b0 | b1) == 0) {
-                    if (ts + LEAF_W >= mrem) { cc++; continue; }  // zero in every remaining row
+                const int es = tt - tsu;   // < 64: pivots fill the window from its start
+                if (b0) {
+                    // pivot in the first half, at entry fl >= es.  Rows with a one in
+                    // column cc other than the pivot add the pivot row on the columns
+                    // right of cc: column j > cc flips them where the pivot has a one.
+                    const int fl = __ffsll((unsigned long long)b0) - 1;
+                    const uint64_t E0 = b0 & ~(1ull << fl);
+                    if (lane > cc && ((c0 >> fl) & 1ull)) {
+                        c0 ^= E0;
+                        c1 ^= b1;
+                    }
+                    if (fl != es) {   // transposition of entries es and fl
+                        const uint64_t d = ((c0 >> es) ^ (c0 >> fl)) & 1ull;
+                        c0 ^= (d << es) | (d << fl);
+                        const int ogs = __builtin_amdgcn_readlane(og0, es);
+                        const int oge = __builtin_amdgcn_readlane(og0, fl);
+                        og0 = lane == es ? oge : (lane == fl ? ogs : og0);
+                    }
+                    fer = lane == cc ? fl : fer;
+                } else if (b1) {
+                    // pivot in the second half, at entry 64 + fl (no first-half row has a one)
+                    const int fl = __ffsll((unsigned long long)b1) - 1;
+                    const uint64_t E1 = b1 & ~(1ull << fl);
+                    if (lane > cc && ((c1 >> fl) & 1ull)) c1 ^= E1;
+                    const uint64_t d = ((c0 >> es) ^ (c1 >> fl)) & 1ull;
+                    c0 ^= d << es;
+                    c1 ^= d << fl;
+                    const int ogs = __builtin_amdgcn_readlane(og0, es);
+                    const int oge = __builtin_amdgcn_readlane(og1, fl);
+                    og0 = lane == es ? oge : og0;
+                    og1 = lane == fl ? ogs : og1;
+                    fer = lane == cc ? 64 + fl : fer;
+                } else {
+                    if (ts + LEAF_W >= mrem) {   // zero in every remaining row
+                        cc++;
+                        continue;
+                    }
                     brk = 1;
                     break;
                 }
-                // first candidate with a one: entry fe = fl (+ 64 if in the second half)
-                const bool in1 = b0 == 0;
-                const uint64_t bb = in1 ? b1 : b0;
-                const int fl = __ffsll((unsigned long long)bb) - 1;
-                const int fe = fl + (in1 ? 64 : 0);
-                const int es = tt - ts;   // < 64: pivots fill the window from its start
-                const uint64_t fbit = 1ull << fl;
-                // rows with a one in column cc other than the pivot add the pivot row on
-                // the columns right of cc: column j > cc flips them where the pivot has a one
-                const uint64_t E0 = in1 ? b0 : (b0 & ~fbit);
-                const uint64_t E1 = in1 ? (b1 & ~fbit) : b1;
-                const uint64_t src = in1 ? c1 : c0;
-                const bool flip = lane > cc && ((src >> fl) & 1ull);
-                c0 ^= flip ? E0 : 0ull;
-                c1 ^= flip ? E1 : 0ull;
-                // transposition of entries es and fe (no-op when equal)
-                const uint64_t src2 = in1 ? c1 : c0;
-                const uint64_t d = ((c0 >> es) ^ (src2 >> fl)) & 1ull;
-                c0 ^= (d << es) ^ (in1 ? 0ull : (d << fl));
-                c1 ^= in1 ? (d << fl) : 0ull;
-                const int ogs = __builtin_amdgcn_readlane(og0, es);
-                const int oge = in1 ? __builtin_amdgcn_readlane(og1, fl)
-                                    : __builtin_amdgcn_readlane(og0, fl);
-                og0 = lane == es ? oge : og0;
-                og0 = (!in1 && lane == fl) ? ogs : og0;
-                og1 = (in1 && lane == fl) ? ogs : og1;
-                fer = lane == cc ? fe : fer;
                 m0 &= ~(1ull << es);
                 tt++;
                 cc++;
