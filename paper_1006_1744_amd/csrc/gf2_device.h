@@ -67,6 +67,25 @@ __device__ inline uint64_t tri_inverse64(const uint64_t *rows, int lane, bool lo
     return tri_inverse64_row(rows[lane], lane, lower);
 }
 
+// Tables of all 256 combinations of each 8 consecutive rows of 64 one-word rows
+// (8 groups): T[g * 256 + e] = XOR of rows 8g + u with bit u of e set.  The
+// threads are split into 8 sets, set g building group g from its 8 rows held
+// in registers; one barrier.  nthr must be a multiple of 8.
+__device__ inline void build_tables_8x8(const uint64_t *rows, uint64_t *T, int tid, int nthr) {
+    const int tpg = nthr >> 3;
+    const int g = tid / tpg;
+    uint64_t rr[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) rr[u] = rows[8 * g + u];
+    for (int e = tid - g * tpg; e < 256; e += tpg) {
+        uint64_t v = 0;
+#pragma unroll
+        for (int u = 0; u < 8; u++) v ^= ((e >> u) & 1) ? rr[u] : 0ull;
+        T[g * 256 + e] = v;
+    }
+    __syncthreads();
+}
+
 // Tables of all 16 combinations of each 4 consecutive rows, built directly
 // (each entry the XOR of at most 4 rows, one barrier at the end): for group g,
 // T[(g * 16 + e) * TW + w] = XOR of rows 4g + u with bit u of e set (rows past
@@ -99,6 +118,21 @@ __device__ inline void build_group_tables(const uint64_t *rows, int nrows, int k
     const int esz = 1 << k;
     const int wq = tid % TW, pq = tid / TW, pstep = nthr / TW;
     const bool on = pq < pstep;
+    if (k <= 4) {
+        // few rows per group: every entry directly (at most 4 loads), one barrier
+        if (on)
+            for (int p = pq; p < ng * esz; p += pstep) {
+                const int g = p >> k, comb = p & (esz - 1);
+                uint64_t v = 0;
+                for (int u = 0; u < k; u++) {
+                    const int row = g * k + u;
+                    if (((comb >> u) & 1) && row < nrows) v ^= rows[row * TW + wq];
+                }
+                T[(size_t)p * TW + wq] = v;
+            }
+        __syncthreads();
+        return;
+    }
     if (on)
         for (int g = pq; g < ng; g += pstep) T[(size_t)g * esz * TW + wq] = 0ull;
     __syncthreads();

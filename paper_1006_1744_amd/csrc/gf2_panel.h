@@ -45,29 +45,38 @@ struct PanelInfo {
     int32_t moved[kMovedInts];
 #ifdef GF2_TRACE
     uint64_t trace[16];
+    uint64_t trace_post[8];
+    uint64_t trace_upd[8];
 #endif
 };
 
 // Build tables for pivots [ta, tb) (consecutive columns q[ta], q[ta]+1, ...):
 // group g holds pivots ta+8g .. ; entry [key] added to a row whose group bits
-// read `key` clears them to the multipliers and reduces the bits above.
+// read `key` clears them to the multipliers and reduces the bits above.  The
+// threads are split into 8 sets, set g building group g: a thread reads its
+// group's 8 (masked) pivot rows from LDS once, then forms its entries from
+// registers.  nthr must be a multiple of 8.
 __device__ inline void build_tables(const uint64_t *U, const int32_t *q, int ta, int tb,
-                             uint64_t (*T)[256], int tid, int nthr) {
-    int np = tb - ta;
-    int ng = (np + 7) >> 3;
-    for (int e = tid; e < ng * 256; e += nthr) {
-        int g = e >> 8, comb = e & 255;
-        int gs = min(8, np - 8 * g);
-        if (comb >= (1 << gs)) continue;
+                                    uint64_t (*T)[256], int tid, int nthr) {
+    const int np = tb - ta;
+    const int ng = (np + 7) >> 3;
+    const int tpg = nthr >> 3;
+    const int g = tid / tpg;
+    if (g >= ng) return;
+    const int gs = min(8, np - 8 * g);
+    uint64_t uu[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const int s = min(ta + 8 * g + u, tb - 1);   // in range for every u
+        const uint64_t keep = u < gs ? ~0ull : 0ull;
+        uu[u] = U[s] & (~0ull << (q[s] & 63)) & keep;
+    }
+    const int off = q[ta] + 8 * g;
+    for (int comb = tid - g * tpg; comb < (1 << gs); comb += tpg) {
         uint64_t v = 0;
-        for (int u = 0; u < gs; u++) {
-            if ((comb >> u) & 1) {
-                int s = ta + 8 * g + u;
-                v ^= U[s] & (~0ull << q[s]);
-            }
-        }
-        int off = q[ta] + 8 * g;
-        int key = (int)((v >> off) & ((1u << gs) - 1));
+#pragma unroll
+        for (int u = 0; u < 8; u++) v ^= ((comb >> u) & 1) ? uu[u] : 0ull;
+        const int key = (int)((v >> off) & ((1u << gs) - 1));
         T[g][key] = v ^ ((uint64_t)comb << off);
     }
 }

@@ -11,7 +11,6 @@
 // (lane group, byte) -> K mapping, so the hardware sums each of the 64 K-bits of
 // a word exactly once.  |a b| <= 128 * 128 and K <= 65536 per call keep the
 // int32 sum far from overflow, and two's complement parity is the LSB anyway.
-#include <stdlib.h>
 
 #include "gf2_internal.h"
 
@@ -286,11 +285,10 @@ hipError_t launch_gemm_mfma(uint64_t *C, int64_t sc, const uint64_t *A, int64_t 
                             int32_t *prof, hipStream_t st) {
     int nkw = (kmax + 63) / 64;
     if (nw <= 0 || nkw <= 0) return hipSuccess;
-    static const int small_only = [] {
-        const char *e = getenv("GF2_MFMA_SMALL_TILE");
-        return e && e[0] == '1';
-    }();
-    if (nw >= 4 && !small_only) {
+    // 256 x 256 tiles pay off once the inner dimension is long enough to hide
+    // their larger prologue and epilogue (measured: K >= 8192 on 65536^2 PLS);
+    // shorter products use the 128 x 128 kernel
+    if (nw >= 4 && kmax > 4096) {
         int64_t tiles = (int64_t)((m + G2_TM - 1) / G2_TM) * ((nw * 64 + G2_TN - 1) / G2_TN);
         int64_t blocks = tiles < 1024 ? tiles : 1024;
         if (blocks >= 8) blocks = blocks / 8 * 8;

@@ -43,6 +43,12 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
     const int R = rk[b];
     const int mrem = m - R;
     if (mrem <= 0) return;
+#ifdef GF2_TRACE
+#define TRP(i) do { if (threadIdx.x == 0 && (blockIdx.x == 0 || (int)blockIdx.x == nfin)) const_cast<PanelInfo *>(info)->trace_post[(i) + ((int)blockIdx.x == nfin ? 4 : 0)] = __builtin_amdgcn_s_memrealtime(); } while (0)
+#else
+#define TRP(i) do {} while (0)
+#endif
+    TRP(0);
     const int r = info->r, F = info->F, pa = info->pa, cmp = info->compress;
     if ((int)blockIdx.x < nfin) {
         const bool pend = (F < mrem) && (r > pa);
@@ -52,8 +58,10 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
             sQ[tid] = info->q[tid];
         }
         __syncthreads();
+        TRP(1);
         if (pend) build_tables(sU, sQ, pa, r, sT, tid, POST_THREADS);
         __syncthreads();
+        TRP(2);
         uint64_t *col = A + (int64_t)R * stride + wc;
         const int step = nfin * POST_THREADS * POST_ROWS;
         for (int base = blockIdx.x * POST_THREADS * POST_ROWS; base < mrem; base += step) {
@@ -83,6 +91,7 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
                 if (w != v[u]) col[(int64_t)o * stride] = w;
             }
         }
+        TRP(3);
         return;
     }
     const int32_t *mv = info->moved;
@@ -94,12 +103,14 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
     }
     if (tid < 64) sPk[tid] = -1;
     __syncthreads();
+    TRP(1);
     if (tid < nk && sDst[tid] < 64) sPk[sDst[tid]] = tid;
     for (int e = tid; e < nk * SWAP_W; e += POST_THREADS) {
         const int k = e / SWAP_W, w = w0 + e % SWAP_W;
         if (w < nwords && w != wc) stage[e] = A[(int64_t)(R + sSrc[k]) * stride + w];
     }
     __syncthreads();
+    TRP(2);
     for (int e = tid; e < nk * SWAP_W; e += POST_THREADS) {
         const int k = e / SWAP_W, w = w0 + e % SWAP_W;
         if (w < nwords && w != wc) A[(int64_t)(R + sDst[k]) * stride + w] = stage[e];
@@ -116,6 +127,7 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
                 k >= 0 ? stage[k * SWAP_W + (w - w0)] : A[(int64_t)(R + t) * stride + w];
         }
     }
+    TRP(3);
 }
 
 hipError_t launch_leaf(uint64_t *A, int64_t stride, int m, int n, int wc, int32_t *rk, int b,

@@ -270,6 +270,13 @@ size_t table_update_lds_bytes(int k, int tables, int TW) {
 __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
     uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk, int b, int w_lo, int w_hi,
     int k, int tables, int TW, const uint64_t *linv, const uint64_t *Bbuf, int64_t bstride) {
+#ifdef GF2_TRACE
+    uint64_t *trace_upd = reinterpret_cast<uint64_t *>(const_cast<char *>(reinterpret_cast<const char *>(linv)) + 64 * 8 + 4 * 257 + 4 + 16 * 8 + 8 * 8);
+#define TRU(i) do { if (threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0 && b == 0) trace_upd[i] = __builtin_amdgcn_s_memrealtime(); } while (0)
+#else
+#define TRU(i) do {} while (0)
+#endif
+    TRU(0);
     extern __shared__ uint64_t tu_lds[];
     uint64_t *sLT = tu_lds;                 // [8][256]   combinations of L^{-1} rows
     uint64_t *sInv = sLT + 8 * 256;         // [64]
@@ -295,7 +302,9 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
             sU[t * TW + wq] = 0ull;
         }
     __syncthreads();
-    build_group_tables(sInv, 64, 8, 8, sLT, 1, tid, TU_THREADS);
+    TRU(1);
+    build_tables_8x8(sInv, sLT, tid, TU_THREADS);
+    TRU(2);
     const int ng = (r + k - 1) / k;
     const int npass = (ng + tables - 1) / tables;
     const int esz = 1 << k;
@@ -323,6 +332,7 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
                 if (chunk > 0 || pass > 0) __syncthreads();
                 build_group_tables(sB + (size_t)g0 * k * TW, r - g0 * k, k, g1 - g0, sT, TW, tid,
                                    TU_THREADS);
+                TRU(3);
                 if (pivots_here && chunk == 0 && pq < pstep) {
                     for (int t = pq; t < r; t += pstep) {
                         const uint64_t ct = sInv[t];
@@ -348,8 +358,10 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
                 if (w < tw_n) px[w] = x[w];
         }
     }
+    TRU(4);
     if (pivots_here && pq < pstep && wq < tw_n)
         for (int t = pq; t < r; t += pstep) A[(int64_t)(R + t) * stride + w0 + wq] = sU[t * TW + wq];
+    TRU(5);
 }
 
 hipError_t launch_table_update(uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk,
