@@ -44,7 +44,7 @@ struct PanelInfo {
     uint64_t linv[64];  // rows of L^{-1} for the panel's r x r unit lower triangle
     int32_t moved[kMovedInts];
 #ifdef GF2_TRACE
-    uint64_t trace[16];
+    uint64_t trace[24];
     uint64_t trace_post[8];
     uint64_t trace_upd[8];
 #endif
@@ -117,9 +117,11 @@ struct SearchLds {
 
 // Search of the panel at word column wc over rows [R, m).  Writes P and Q at
 // the pivot slots R + t, the window rows' and scanned rows' panel words, and
-// *info (r, F, pa, compress, q, u, linv, moved).  Returns r (in every thread).
+// *info (r, F, pa, compress, q, u, linv, moved), and L^{-1} also to linv_out
+// (64 words) when given.  Returns r (in every thread).
 __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, int wc, int R,
-                                   int32_t *P, int32_t *Q, PanelInfo *info, SearchLds &S) {
+                                   int32_t *P, int32_t *Q, PanelInfo *info, SearchLds &S,
+                                   uint64_t *linv_out = nullptr) {
     uint64_t *sU = S.sU;
     int32_t *sQ = S.sQ;
     int32_t *sPrel = S.sPrel;
@@ -138,7 +140,7 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
 
 #ifdef GF2_TRACE
     int ntr = 0;
-#define TR() do { if (tid == 0 && ntr < 14) { info->trace[ntr++] = __builtin_amdgcn_s_memrealtime(); info->trace[ntr++] = __builtin_amdgcn_s_memtime(); } } while (0)
+#define TR() do { if (tid == 0 && ntr < 22) { info->trace[ntr++] = __builtin_amdgcn_s_memrealtime(); info->trace[ntr++] = __builtin_amdgcn_s_memtime(); } } while (0)
 #else
 #define TR() do {} while (0)
 #endif
@@ -402,28 +404,37 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
         // L (r x r, pivot order): L[t][s] is bit q[s] of the pivot word sU[t].
         // Lane j solves L x = e_j column by column (x ^= L[:, s] where x[s] = 1),
         // then the columns of L^{-1} are transposed into rows.  Identity past r.
-        const uint64_t urow = lane < r ? sU[lane] : 0ull;
+        // The pivot columns sit one per lane, so the loop reads them by readlane.
+        const int ru = __builtin_amdgcn_readfirstlane(r);
+        const uint64_t urow = lane < ru ? sU[lane] : 0ull;
+        const int qv = lane < ru ? sQ[lane] : lane;
+        // Straight-line and unrolled so that the column ballots, which do not
+        // depend on x, can be issued ahead of the substitution chain; columns
+        // s >= r - 1 are empty (no lane below r passes the test), so every step
+        // may run.
         uint64_t xcol = 1ull << lane;
-        for (int s2 = 0; s2 + 1 < r; s2++) {
-            const int qs = sQ[s2];
-            const uint64_t Lcol = __ballot(lane > s2 && lane < r && ((urow >> qs) & 1ull));
-            if ((xcol >> s2) & 1ull) xcol ^= Lcol;
+#pragma unroll
+        for (int s2 = 0; s2 < 63; s2++) {
+            const int qs = __builtin_amdgcn_readlane(qv, s2);
+            const uint64_t Lcol = __ballot(lane > s2 && lane < ru && ((urow >> qs) & 1ull));
+            xcol ^= ((xcol >> s2) & 1ull) ? Lcol : 0ull;
         }
-        info->linv[lane] = transpose64(xcol, lane);
-        info->q[lane] = lane < r ? sQ[lane] : lane;
+        const uint64_t lrow = transpose64(xcol, lane);
+        info->linv[lane] = lrow;
+        if (linv_out) linv_out[lane] = lrow;
+        info->q[lane] = qv;
         info->u[lane] = urow;
-    }
-    if (tid == 0) {
-        int cmp = 0;
-        for (int s2 = 0; s2 < r; s2++) cmp |= (sQ[s2] != s2);
-        info->r = r;
-        info->F = max(0, min(s_F, mrem));
-        info->pa = min(s_pa, r);
-        info->compress = cmp;
+        const uint64_t moved_cols = __ballot(lane < ru && qv != lane);
+        if (lane == 0) {
+            info->r = r;
+            info->F = max(0, min(s_F, mrem));
+            info->pa = min(s_pa, r);
+            info->compress = moved_cols != 0;
+        }
     }
     TR();
 #ifdef GF2_TRACE
-    if (tid == 0) info->trace[15] = ntr;
+    if (tid == 0) info->trace[23] = ntr;
 #endif
     __syncthreads();
     return r;

@@ -10,11 +10,12 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
     int32_t *Q, PanelInfo *info, uint64_t *linv_store) {
     __shared__ SearchLds S;
     const int R = rk[b];
-    const int r = panel_search(A, stride, m, n, wc, R, P, Q, info, S);
+    const int r = panel_search(A, stride, m, n, wc, R, P, Q, info, S,
+                               linv_store ? linv_store + (int64_t)b * 64 : nullptr);
     if (threadIdx.x == 0) rk[b + 1] = R + r;
-    // the panel's L^{-1}, kept per panel for the triangular solves above it
-    if (linv_store && threadIdx.x < 64)
-        linv_store[(int64_t)b * 64 + threadIdx.x] = info->linv[threadIdx.x];
+#ifdef GF2_TRACE
+    if (threadIdx.x == 0) info->trace[20] = __builtin_amdgcn_s_memrealtime();
+#endif
 }
 
 // Final pass over the panel (blocks [0, nfin)) and the other word columns of

@@ -271,7 +271,7 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
     uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk, int b, int w_lo, int w_hi,
     int k, int tables, int TW, const uint64_t *linv, const uint64_t *Bbuf, int64_t bstride) {
 #ifdef GF2_TRACE
-    uint64_t *trace_upd = reinterpret_cast<uint64_t *>(const_cast<char *>(reinterpret_cast<const char *>(linv)) + 64 * 8 + 4 * 257 + 4 + 16 * 8 + 8 * 8);
+    uint64_t *trace_upd = reinterpret_cast<uint64_t *>(const_cast<char *>(reinterpret_cast<const char *>(linv)) + 64 * 8 + 4 * 257 + 4 + 24 * 8 + 8 * 8);
 #define TRU(i) do { if (threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0 && b == 0) trace_upd[i] = __builtin_amdgcn_s_memrealtime(); } while (0)
 #else
 #define TRU(i) do {} while (0)
