@@ -50,6 +50,7 @@ namespace {
 constexpr int64_t kMaxDim = (int64_t)1 << 30;
 constexpr int kMfmaMaxK = 65536;   // int32 sums of +-128*128 products stay exact
 constexpr int kINF = 0x3fffffff;
+constexpr int kBufWords = 16;       // widest base block worked on in a contiguous copy
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -146,6 +147,8 @@ struct PlsDriver {
     uint64_t *Bt = nullptr;
     uint64_t *Bbuf = nullptr;         // staged pivot rows, 64 x bstride words
     uint64_t *linv_store = nullptr;   // per panel: L^{-1} of its pivot block (64 words)
+    uint64_t *pbuf = nullptr;         // base block copy: m rows x pbuf_w words, contiguous
+    int pbuf_w = 0;
     int64_t bstride = 0;
     int cus = 256;
     size_t bt_words = 0;   // capacity (launch) or requirement (dry)
@@ -191,17 +194,25 @@ struct PlsDriver {
     // rows below, on the block's remaining columns.
     void base(int wb, int nwd) {
         if (dry) bstride = std::max<int64_t>(bstride, nwd - 1);
+        // a narrow block works on a contiguous copy of its words (rows of nwd words),
+        // so the passes over the rows below a panel read whole segments in order
+        const bool buffered = pbuf_w > 0 && nwd <= pbuf_w && nwd > 1;
+        uint64_t *Ab = buffered ? pbuf - wb : A;
+        const int64_t sb = buffered ? nwd : stride;
+        const int blk_lo = buffered ? wb : 0, blk_hi = buffered ? wb + nwd : (int)stride;
+        if (buffered && !dry) chk(launch_copy_rows(pbuf, nwd, 0, A, stride, wb, nwd, rk, wb, m, st));
         for (int p = 0; p < nwd; p++) {
             const int wc = wb + p;
             const bool upd = p + 1 < nwd;
             if (!dry)
-                chk(launch_leaf(A, stride, m, n, wc, rk, wc, P, Q, info, upd ? Bbuf : nullptr,
-                                bstride, wc + 1, wb + nwd, linv_store, st));
+                chk(launch_leaf(A, stride, Ab, sb, blk_lo, blk_hi, m, n, wc, rk, wc, P, Q, info,
+                                upd ? Bbuf : nullptr, bstride, wc + 1, wb + nwd, linv_store, st));
             if (upd && !dry)
-                chk(launch_table_update(A, stride, m, wc, rk, wc, wc + 1, wb + nwd, s.k, s.tables,
-                                        linv, Bbuf, bstride, cus, st));
+                chk(launch_table_update(Ab, sb, m, wc, rk, wc, wc + 1, wb + nwd, s.k, s.tables, linv,
+                                        Bbuf, bstride, cus, st));
         }
-        if (!dry) chk(launch_compress_chain(A, stride, m, wb, nwd, rk, st));
+        if (!dry) chk(launch_compress_chain(Ab, sb, m, wb, nwd, rk, buffered ? wb + nwd : stride, st));
+        if (buffered && !dry) chk(launch_copy_rows(A, stride, wb, pbuf, nwd, 0, nwd, rk, wb, m, st));
     }
 
     void node(int wb, int nwd) {
@@ -229,7 +240,8 @@ struct PlsDriver {
 };
 
 struct PlsLayout {
-    size_t rk_off, info_off, bt_off, bb_off, linv_off, total;
+    size_t rk_off, info_off, bt_off, bb_off, linv_off, pbuf_off, total;
+    int pbuf_w;
     size_t bt_words;
     int64_t bstride;
 };
@@ -256,6 +268,9 @@ PlsLayout pls_layout(int64_t m, int64_t n, const gf2_sched &s) {
     off = align_up(off + (size_t)64 * L.bstride * 8);
     L.linv_off = off;
     off = align_up(off + (size_t)(d.nb + 1) * 64 * 8);
+    L.pbuf_w = std::min(std::min(s.cutoff / 64, kBufWords), d.nb);
+    L.pbuf_off = off;
+    off = align_up(off + (size_t)std::max<int64_t>(m, 1) * std::max(L.pbuf_w, 1) * 8);
     L.total = off;
     return L;
 }
@@ -415,6 +430,8 @@ int gf2_pls(gf2_ctx *ctx, gf2_mat A, int32_t *P, int32_t *Q, int32_t *rank, cons
     d.bstride = L.bstride;
     d.linv = (const uint64_t *)(base + L.info_off + panel_info_linv_offset());
     d.linv_store = (uint64_t *)(base + L.linv_off);
+    d.pbuf = (uint64_t *)(base + L.pbuf_off);
+    d.pbuf_w = L.pbuf_w;
     d.cus = ctx->cus;
     d.P = P;
     d.Q = Q;

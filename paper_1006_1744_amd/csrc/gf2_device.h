@@ -154,8 +154,9 @@ __device__ inline void build_group_tables(const uint64_t *rows, int nrows, int k
 // at n0 (both multiples of 64): the second block's L columns [c0+n0, c0+n0+r1)
 // move to [c0+r0, c0+r0+r1) as the column swaps "i <-> n0 + (i - r0), from row
 // i" of Section 5 leave them: a row at offset v below the first block's pivots
-// moves min(v + 1, r1) columns and zeroes the vacated ones.
-__device__ inline void shift_row(uint64_t *row, int64_t stride, int c0, int n0, int r0, int r1,
+// moves min(v + 1, r1) columns and zeroes the vacated ones.  Words at index
+// >= wlim are not read (the row's extent).
+__device__ inline void shift_row(uint64_t *row, int64_t wlim, int c0, int n0, int r0, int r1,
                                  int v) {
     const int d = n0 - r0;
     const int len = min(v + 1, r1);
@@ -166,8 +167,8 @@ __device__ inline void shift_row(uint64_t *row, int64_t stride, int c0, int n0, 
         const int p0 = w * 64;
         const int sb = p0 + d;         // source of position p0
         const int sw = sb >> 6, so = sb & 63;
-        const uint64_t lo = sw < stride ? row[sw] : 0ull;
-        const uint64_t hi = (so && sw + 1 < stride) ? row[sw + 1] : 0ull;
+        const uint64_t lo = sw < wlim ? row[sw] : 0ull;
+        const uint64_t hi = (so && sw + 1 < wlim) ? row[sw + 1] : 0ull;
         const uint64_t src = so ? ((lo >> so) | (hi << (64 - so))) : lo;
         const uint64_t old = row[w];
         uint64_t mv = 0, clr = 0;

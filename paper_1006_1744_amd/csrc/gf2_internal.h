@@ -50,6 +50,10 @@ constexpr int kMovedInts = 1 + 2 * kMaxMoved;
 // All return hipError_t of the launch.
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st);
 
+// The words [blk_lo, blk_hi) of every row may live in a separate array (Ab, row
+// stride sb, indexed by the same row and word numbers); the search, the final
+// pass and the staging of the pivot rows use it, the moves of the other words
+// use (A, stride).  Pass Ab = A, sb = stride and the whole width to work in place.
 // Panel factorisation of the 64-column panel at word column wc, rows
 // [rk[b], m): pivots, row swaps inside the panel, L of every row, compressed.
 // Writes rk[b + 1], P and Q at the pivot slots, and the moved-row list.
@@ -57,9 +61,10 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t st)
 // `info` is a device scratch record of panel_info_bytes() bytes.
 // The pivot rows' words on [bw_lo, bw_hi) are copied (after the swaps) into
 // Bbuf (row t at Bbuf + t * bstride) when Bbuf is non-null.
-hipError_t launch_leaf(uint64_t *A, int64_t stride, int m, int n, int wc, int32_t *rk, int b,
-                       int32_t *P, int32_t *Q, int32_t *info, uint64_t *Bbuf, int64_t bstride,
-                       int bw_lo, int bw_hi, uint64_t *linv_store, hipStream_t st);
+hipError_t launch_leaf(uint64_t *A, int64_t stride, uint64_t *Ab, int64_t sb, int blk_lo,
+                       int blk_hi, int m, int n, int wc, int32_t *rk, int b, int32_t *P, int32_t *Q,
+                       int32_t *info, uint64_t *Bbuf, int64_t bstride, int bw_lo, int bw_hi,
+                       uint64_t *linv_store, hipStream_t st);
 size_t panel_info_bytes();
 size_t panel_info_linv_offset();
 
@@ -98,7 +103,7 @@ hipError_t launch_compress_shift(uint64_t *A, int64_t stride, int m, int c0, int
 // All shifts of an MMPF block of nwd panels at word wb (splits after each panel),
 // innermost first.
 hipError_t launch_compress_chain(uint64_t *A, int64_t stride, int m, int wb, int nwd,
-                                 const int32_t *rk, hipStream_t st);
+                                 const int32_t *rk, int64_t wlim, hipStream_t st);
 
 // P[i] = i for i >= r, Q[i] = i for r <= i < n, *rank = r, with r = rk[nb].
 hipError_t launch_finalize(int32_t *P, int32_t *Q, int32_t *rank, const int32_t *rk, int nb,
@@ -141,6 +146,9 @@ hipError_t launch_rref_scatter(uint64_t *R, int64_t sr, int m, int n, const int3
 // blocks.  ws holds batch_ws_bytes(count) bytes.
 size_t batch_ws_bytes(int64_t count);
 hipError_t mlp_prepare();
+// Rows [rk[ib], m) x nw words: dst word (i, dw0 + j) <- src word (i, sw0 + j).
+hipError_t launch_copy_rows(uint64_t *dst, int64_t sd, int dw0, const uint64_t *src, int64_t ss,
+                            int sw0, int nw, const int32_t *rk, int ib, int m, hipStream_t st);
 hipError_t launch_unpack(const uint64_t *A, int64_t sa, int m, int n, const int32_t *Q,
                          const int32_t *rank, uint64_t *L, int64_t sl, int lwords, uint64_t *S,
                          int64_t ss, int swords, int64_t max_words, hipStream_t st);

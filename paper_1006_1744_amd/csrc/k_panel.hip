@@ -32,8 +32,9 @@ constexpr int POST_ROWS = 4;
 constexpr int SWAP_W = 16;
 
 __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
-    uint64_t *A, int64_t stride, int m, int wc, int nwords, const int32_t *rk, int b,
-    const PanelInfo *info, int nfin, uint64_t *Bbuf, int64_t bstride, int bw_lo, int bw_hi) {
+    uint64_t *A, int64_t stride, uint64_t *Ab, int64_t sb, int blk_lo, int blk_hi, int m, int wc,
+    int nwords, const int32_t *rk, int b, const PanelInfo *info, int nfin, uint64_t *Bbuf,
+    int64_t bstride, int bw_lo, int bw_hi) {
     __shared__ uint64_t sT[8][256];
     __shared__ uint64_t sU[64];
     __shared__ int32_t sQ[64];
@@ -63,14 +64,14 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
         if (pend) build_tables(sU, sQ, pa, r, sT, tid, POST_THREADS);
         __syncthreads();
         TRP(2);
-        uint64_t *col = A + (int64_t)R * stride + wc;
+        uint64_t *col = Ab + (int64_t)R * sb + wc;   // the panel word lies in the block
         const int step = nfin * POST_THREADS * POST_ROWS;
         for (int base = blockIdx.x * POST_THREADS * POST_ROWS; base < mrem; base += step) {
             uint64_t v[POST_ROWS];
 #pragma unroll
             for (int u = 0; u < POST_ROWS; u++) {
                 const int o = base + u * POST_THREADS + tid;
-                v[u] = o < mrem ? col[(int64_t)o * stride] : 0ull;
+                v[u] = o < mrem ? col[(int64_t)o * sb] : 0ull;
             }
 #pragma unroll
             for (int u = 0; u < POST_ROWS; u++) {
@@ -89,7 +90,7 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
                         }
                     }
                 }
-                if (w != v[u]) col[(int64_t)o * stride] = w;
+                if (w != v[u]) col[(int64_t)o * sb] = w;
             }
         }
         TRP(3);
@@ -106,15 +107,19 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
     __syncthreads();
     TRP(1);
     if (tid < nk && sDst[tid] < 64) sPk[sDst[tid]] = tid;
+    // words of the block live in (Ab, sb), the others in (A, stride)
+    auto wp = [&](int row, int w) -> uint64_t * {
+        return (w >= blk_lo && w < blk_hi) ? Ab + (int64_t)row * sb + w : A + (int64_t)row * stride + w;
+    };
     for (int e = tid; e < nk * SWAP_W; e += POST_THREADS) {
         const int k = e / SWAP_W, w = w0 + e % SWAP_W;
-        if (w < nwords && w != wc) stage[e] = A[(int64_t)(R + sSrc[k]) * stride + w];
+        if (w < nwords && w != wc) stage[e] = *wp(R + sSrc[k], w);
     }
     __syncthreads();
     TRP(2);
     for (int e = tid; e < nk * SWAP_W; e += POST_THREADS) {
         const int k = e / SWAP_W, w = w0 + e % SWAP_W;
-        if (w < nwords && w != wc) A[(int64_t)(R + sDst[k]) * stride + w] = stage[e];
+        if (w < nwords && w != wc) *wp(R + sDst[k], w) = stage[e];
     }
     // the pivot rows' words on [bw_lo, bw_hi) after the moves: a moved pivot row
     // takes the staged copy, any other is not written by this launch
@@ -125,19 +130,19 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
             const int t = e / bw, w = blo + e % bw;
             const int k = sPk[t];
             Bbuf[(int64_t)t * bstride + (w - bw_lo)] =
-                k >= 0 ? stage[k * SWAP_W + (w - w0)] : A[(int64_t)(R + t) * stride + w];
+                k >= 0 ? stage[k * SWAP_W + (w - w0)] : *wp(R + t, w);
         }
     }
     TRP(3);
 }
 
-hipError_t launch_leaf(uint64_t *A, int64_t stride, int m, int n, int wc, int32_t *rk, int b,
-                       int32_t *P, int32_t *Q, int32_t *infobuf, uint64_t *Bbuf,
-                       int64_t bstride, int bw_lo, int bw_hi, uint64_t *linv_store,
-                       hipStream_t st) {
+hipError_t launch_leaf(uint64_t *A, int64_t stride, uint64_t *Ab, int64_t sb, int blk_lo,
+                       int blk_hi, int m, int n, int wc, int32_t *rk, int b, int32_t *P, int32_t *Q,
+                       int32_t *infobuf, uint64_t *Bbuf, int64_t bstride, int bw_lo, int bw_hi,
+                       uint64_t *linv_store, hipStream_t st) {
     PanelInfo *info = reinterpret_cast<PanelInfo *>(infobuf);
-    hipLaunchKernelGGL(leaf_search_kernel, dim3(1), dim3(LEAF_THREADS), 0, st, A, stride, m, n,
-                       wc, rk, b, P, Q, info, linv_store);
+    hipLaunchKernelGGL(leaf_search_kernel, dim3(1), dim3(LEAF_THREADS), 0, st, Ab, sb, m, n, wc, rk,
+                       b, P, Q, info, linv_store);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int nwords = (n + 63) / 64;
@@ -145,8 +150,9 @@ hipError_t launch_leaf(uint64_t *A, int64_t stride, int m, int n, int wc, int32_
     if (nfin > 256) nfin = 256;
     if (nfin < 1) nfin = 1;
     int nswap = (nwords + SWAP_W - 1) / SWAP_W;
-    hipLaunchKernelGGL(panel_post_kernel, dim3(nfin + nswap), dim3(POST_THREADS), 0, st, A,
-                       stride, m, wc, nwords, rk, b, info, nfin, Bbuf, bstride, bw_lo, bw_hi);
+    hipLaunchKernelGGL(panel_post_kernel, dim3(nfin + nswap), dim3(POST_THREADS), 0, st, A, stride,
+                       Ab, sb, blk_lo, blk_hi, m, wc, nwords, rk, b, info, nfin, Bbuf, bstride, bw_lo,
+                       bw_hi);
     return hipGetLastError();
 }
 

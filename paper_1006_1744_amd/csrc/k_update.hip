@@ -56,6 +56,29 @@ hipError_t launch_copy_words(uint64_t *dst, int64_t sd, const uint64_t *src, int
     return hipGetLastError();
 }
 
+// Rows [rk[ib], m) x nw words: dst word (i, dw0 + j) <- src word (i, sw0 + j).
+__global__ void copy_rows_kernel(uint64_t *dst, int64_t sd, int dw0, const uint64_t *src,
+                                 int64_t ss, int sw0, int nw, const int32_t *rk, int ib, int m) {
+    const int r0 = rk[ib];
+    const int64_t total = (int64_t)(m - r0) * nw;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = r0 + e / nw;
+        const int j = (int)(e % nw);
+        dst[i * sd + dw0 + j] = src[i * ss + sw0 + j];
+    }
+}
+
+hipError_t launch_copy_rows(uint64_t *dst, int64_t sd, int dw0, const uint64_t *src, int64_t ss,
+                            int sw0, int nw, const int32_t *rk, int ib, int m, hipStream_t st) {
+    if (nw <= 0 || m <= 0) return hipSuccess;
+    int64_t blocks = ((int64_t)m * nw + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(copy_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, st, dst, sd, dw0, src,
+                       ss, sw0, nw, rk, ib, m);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ TRSM
 // X <- T^{-1} X on at most 64 rows: T^{-1} is formed by one wave (column-wise
 // substitution, tri_inverse64), then every output row is a combination of the
@@ -250,7 +273,7 @@ hipError_t launch_trsm_block(uint64_t *A, int64_t stride, const uint64_t *Lm, in
 // One thread owns one row and all TW (<= TU_TWMAX) words of the block's tile,
 // so l L^{-1} is formed once per row and the row's loads are issued together;
 // the grid is sized to be resident in one round.
-constexpr int TU_THREADS = 256;
+constexpr int TU_THREADS = 1024;   // one row per thread; 16 waves hide the table build's latency
 constexpr int TU_TWMAX = 8;
 constexpr int TU_TABLE_LDS = 120 * 1024;   // budget for the B tables of one pass
 constexpr int TU_LDS_MAX = 150 * 1024;
@@ -326,6 +349,11 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
 #pragma unroll
             for (int g8 = 0; g8 < 8; g8++) c ^= sLT[g8 * 256 + (int)((l >> (8 * g8)) & 255)];
         }
+#ifdef GF2_TRACE
+        if (act && c == 0x123456789ull) x[0] ^= 1;   // keep the loads before the stamp
+        __syncthreads();
+#endif
+        TRU(6);
         for (int pass = 0; pass < npass; pass++) {
             const int g0 = pass * tables, g1 = min(ng, g0 + tables);
             if (chunk == 0 || npass > 1) {
@@ -405,7 +433,7 @@ __global__ void compress_shift_kernel(uint64_t *A, int64_t stride, int m, int c0
 // The shifts of an MMPF block of nwd panels at word wb, innermost first: the
 // block is a right-nested chain of 64-column splits.
 __global__ void compress_chain_kernel(uint64_t *A, int64_t stride, int m, int wb, int nwd,
-                                      const int32_t *rk) {
+                                      const int32_t *rk, int64_t wlim) {
     const int Re = rk[wb + nwd];
     bool any = false;
     for (int p = 0; p + 1 < nwd; p++) {
@@ -419,7 +447,7 @@ __global__ void compress_chain_kernel(uint64_t *A, int64_t stride, int m, int wb
         for (int p = nwd - 2; p >= 0; p--) {
             const int Rp = rk[wb + p], Rm = rk[wb + p + 1];
             const int r0 = Rm - Rp, r1 = Re - Rm;
-            if (r0 < 64 && r1 > 0 && i >= Rm) shift_row(row, stride, 64 * (wb + p), 64, r0, r1, i - Rm);
+            if (r0 < 64 && r1 > 0 && i >= Rm) shift_row(row, wlim, 64 * (wb + p), 64, r0, r1, i - Rm);
         }
     }
 }
@@ -435,13 +463,13 @@ hipError_t launch_compress_shift(uint64_t *A, int64_t stride, int m, int c0, int
 }
 
 hipError_t launch_compress_chain(uint64_t *A, int64_t stride, int m, int wb, int nwd,
-                                 const int32_t *rk, hipStream_t st) {
+                                 const int32_t *rk, int64_t wlim, hipStream_t st) {
     if (nwd < 2) return hipSuccess;
     int blocks = (m + 255) / 256;
     if (blocks > 1024) blocks = 1024;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(compress_chain_kernel, dim3(blocks), dim3(256), 0, st, A, stride, m, wb,
-                       nwd, rk);
+                       nwd, rk, wlim);
     return hipGetLastError();
 }
 
