@@ -36,9 +36,9 @@ INT8_MFMA_PEAK_TOPS = 5000.0   # MI355X dense int8 matrix-core peak (TOP/s)
 # passes over one step (FETCH_SIZE, then WRITE_SIZE), each scaled by what the
 # counter reads for a 1 GiB plain copy in the same run (x2 and x1).  Valid only
 # for the kernel source it was taken with (SHA-256 prefix); otherwise null.
-PMC_TRAFFIC = {"source": "paper_1006_1744_amd/csrc/k_mfma.hip", "sha256_16": "9ecfb312f77a751f",
-               "bytes_per_launch": (30.73 * 2 + 5.52) * 2**20,
-               "profile": "profiles/gemm_mfma2_traffic_65536.md"}
+PMC_TRAFFIC = {"source": "paper_1006_1744_amd/csrc/k_mfma.hip", "sha256_16": "1dace8ad064b943b",
+               "bytes_per_launch": 96766217,
+               "profile": "profiles/gemm_mfma_traffic_65536.md"}
 
 
 def pmc_traffic():
@@ -128,7 +128,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--cpu-n", type=int, default=65536)
+    ap.add_argument("--cpu-n", type=int, default=57344)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-rref", action="store_true")
     ap.add_argument("--sched", type=str, default="")
