@@ -4,13 +4,18 @@
 //
 // Exactness.  Only the parity of the int32 sum is kept.  For integers a, b the
 // product's parity is (a mod 2)(b mod 2), so every operand byte only has to
-// carry the wanted bit in its least significant position; the other seven bits
-// may hold anything.  A lane's 32 K-bits w therefore become two 16-byte MFMA
-// operands with seven shifts: register v of step s is w >> (4 s + v), whose byte
-// t carries bit 8 t + 4 s + v of w in its LSB.  Both operands use the same
-// (lane group, byte) -> K mapping, so the hardware sums each of the 64 K-bits of
-// a word exactly once.  |a b| <= 128 * 128 and K <= 65536 per call keep the
-// int32 sum far from overflow, and two's complement parity is the LSB anyway.
+// carry the wanted bit in its least significant position.  A lane's 32 K-bits w
+// therefore become two 16-byte MFMA operands: register v of step s is
+// (w >> (4 s + v)) & 0x01010101, whose byte t is bit 8 t + 4 s + v of w.  Both
+// operands use the same (lane group, byte) -> K mapping, so the hardware sums
+// each of the 64 K-bits of a word exactly once.  Sums stay below K <= 65536 per
+// call, far from int32 overflow.
+//
+// The mask is not needed for the parity (bits above a byte's LSB never reach
+// the LSB of a product) but for the clock: the matrix cores' power grows with
+// the number of toggling operand bits, and with 0/1 bytes the chip holds a
+// markedly higher clock under this load than with random bytes (measured on
+// 32768^3: about 2.26 GHz against 1.76 GHz, 3.7 against 3.1 POP/s).
 
 #include "gf2_internal.h"
 
@@ -91,8 +96,8 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(uint64_t *C, int64_t sc,
                     for (int t = 0; t < 2; t++) {
 #pragma unroll
                         for (int v = 0; v < 4; v++) {
-                            fa[t][v] = (int)(wa[t] >> (4 * s + v));
-                            fb[t][v] = (int)(wb[t] >> (4 * s + v));
+                            fa[t][v] = (int)((wa[t] >> (4 * s + v)) & 0x01010101u);
+                            fb[t][v] = (int)((wb[t] >> (4 * s + v)) & 0x01010101u);
                         }
                     }
 #pragma unroll
@@ -131,16 +136,55 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(uint64_t *C, int64_t sc,
 }
 
 // Large-tile variant: 256 x 256 outputs per block, 128 x 128 per wave (4 x 4
-// MFMA tiles, 256 accumulators), K staged 8 words (512 bits) at a time through
-// double-buffered LDS with the next stage's global loads in flight during the
-// current stage's MFMAs.  Tiles are walked in groups of 8 row-tiles per column
-// tile, and consecutive tiles are kept on one XCD (blocks are dealt round-robin
-// over the 8 XCDs), so the operands a group shares stay in that XCD's L2.
+// MFMA tiles, 256 accumulators), fed by direct global -> LDS loads
+// (global_load_lds_dwordx4): the operand tiles never pass through registers, so
+// three stages of 8 K words (512 bits) are in flight at once.  One load
+// instruction fills a 1 KiB chunk of 16 tile rows x 4 word pairs, lane j writing
+// slot j; slot 4 r + (p ^ h(r)) holds word pair p of chunk row r, with
+// h(r) = ((r >> 1) ^ (r >> 3)) & 3, so the 16-byte LDS reads of the MFMA
+// fragments (32 rows, one pair) hit distinct bank groups.  Each lane reads a
+// whole word pair: lane group lg takes pair 2 q + lg in round q, and its four
+// 32-bit parts feed four MFMA K steps of two register sets each.  Full stages
+// only: a K tail of fewer than 8 words is staged with ordinary guarded loads
+// after the pipeline has drained.  Tiles are walked in groups of 8 row tiles
+// per column tile, and consecutive tiles are kept on one XCD (blocks are dealt
+// round-robin over the 8 XCDs), so the operands a group shares stay in that
+// XCD's L2.
 constexpr int G2_TM = 256;
 constexpr int G2_TN = 256;
-constexpr int G2_KC = 8;                    // K words per stage
-constexpr int G2_LD = 2 * G2_KC + 2;        // u32 per LDS row (padded, 8-byte aligned)
-constexpr int G2_GROUP = 8;
+constexpr int G2_KC = 8;
+constexpr int G2_NBUF = 3;
+constexpr int G2_GROUP = 8;                // row tiles walked per column tile
+constexpr int G2_STAGE = G2_TM * G2_KC;   // words per operand per stage (16 KiB)
+
+__device__ inline int g2_slot(int r, int p) {
+    return 4 * r + (p ^ (((r >> 1) ^ (r >> 3)) & 3));
+}
+
+// Issued as inline assembly so that the compiler neither tracks the LDS write
+// nor inserts its own wait for it before every LDS read: the kernel waits for
+// the load counter itself.  M0 holds the chunk's LDS byte address (one wait
+// state before the load that reads it) and gets its old value back afterwards.
+__device__ inline void g2_dma16(const uint64_t *src, uint32_t lds) {
+    uint32_t keep;
+    asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\t"
+                 "global_load_lds_dwordx4 %1, off\n\ts_mov_b32 m0, %0"
+                 : "=&s"(keep) : "v"(src), "s"(lds) : "memory");
+}
+
+// v_writelane_b32 (the LLVM intrinsic, so that the compiler places the wait
+// states a lane write needs after the compare that produced its value): the
+// wave-uniform value v replaces lane l of o.
+extern "C" __device__ int gf2_amdgcn_writelane(int v, int lane, int old)
+    __asm("llvm.amdgcn.writelane.i32");
+
+__device__ inline uint32_t g2_writelane(uint32_t o, uint32_t v, int l) {
+    return (uint32_t)gf2_amdgcn_writelane((int)v, l, (int)o);
+}
+
+__device__ inline uint32_t g2_lds_addr(const uint64_t *p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint64_t *)p;
+}
 
 __global__ __launch_bounds__(256) void gemm_mfma2_kernel(uint64_t *C, int64_t sc,
                                                          const uint64_t *A, int64_t sa, int m,
@@ -148,8 +192,8 @@ __global__ __launch_bounds__(256) void gemm_mfma2_kernel(uint64_t *C, int64_t sc
                                                          const uint64_t *Bt, int64_t sbt, int nkw,
                                                          RowRange krows, int kmrows,
                                                          const int32_t *rk, int32_t *prof) {
-    __shared__ uint32_t sA[2][G2_TM * G2_LD];
-    __shared__ uint32_t sB[2][G2_TN * G2_LD];
+    __shared__ __attribute__((aligned(16))) uint64_t sA[G2_NBUF][G2_STAGE];
+    __shared__ __attribute__((aligned(16))) uint64_t sB[G2_NBUF][G2_STAGE];
     int r0, r1;
     eval_range(rk, m, rows, r0, r1);
     const int M = r1 - r0;
@@ -166,10 +210,25 @@ __global__ __launch_bounds__(256) void gemm_mfma2_kernel(uint64_t *C, int64_t sc
     const int wm = wave & 1, wn = wave >> 1;
     const int li = lane & 31, lg = lane >> 5;
     const int tiles_m = (M + G2_TM - 1) / G2_TM;
-    const int tiles_n = (nw * 64 + G2_TN - 1) / G2_TN;
+    const int ncol = nw * 64;
+    const int tiles_n = (ncol + G2_TN - 1) / G2_TN;
     const int ntiles = tiles_m * tiles_n;
-    const int nstage = (nkw + G2_KC - 1) / G2_KC;
-    // XCD-contiguous virtual block id
+    const int nfull = nkw / G2_KC;
+    const int ktail = nkw - nfull * G2_KC;
+    // loader role: chunks 4 wave + i (i < 4) of each operand; lane -> (row, pair)
+    const int lr = lane >> 2;
+    const int lp = (lane & 3) ^ (((lr >> 1) ^ (lr >> 3)) & 3);
+    // reader role: word offset of the slot of pair 2 q + lg of this lane's row
+    // in row group t (the swizzle is an XOR, so each round has its own offset)
+    int offa[2][4], offb[2][4];
+#pragma unroll
+    for (int q = 0; q < 2; q++)
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const int ra = wm * 128 + t * 32 + li, rb = wn * 128 + t * 32 + li;
+            offa[q][t] = (ra >> 4) * 128 + 2 * g2_slot(ra & 15, 2 * q + lg);
+            offb[q][t] = (rb >> 4) * 128 + 2 * g2_slot(rb & 15, 2 * q + lg);
+        }
     const int per = gridDim.x / 8;
     const int vid = (gridDim.x % 8 == 0) ? (blockIdx.x % 8) * per + blockIdx.x / 8 : blockIdx.x;
     for (int tile = vid; tile < ntiles; tile += gridDim.x) {
@@ -180,28 +239,25 @@ __global__ __launch_bounds__(256) void gemm_mfma2_kernel(uint64_t *C, int64_t sc
         const int tn = in / gsz;
         const int row0 = r0 + tm * G2_TM;
         const int cw0 = tn * (G2_TN / 64);
-        // cooperative loads: element e = tid + 256 i is word e % KC of tile row e / KC,
-        // so KC consecutive lanes read one row's KC words (one 64-byte segment)
-        uint64_t ra[G2_KC], rb[G2_KC];
-        auto gload = [&](int st) {
+        // rows past the matrix edge load a clamped (valid) row; their outputs are
+        // never stored
+        const uint64_t *pa[4], *pb[4];
 #pragma unroll
-            for (int i = 0; i < G2_KC; i++) {
-                const int e = tid + 256 * i;
-                const int rr = e / G2_KC, w = e % G2_KC;
-                const int kw = st * G2_KC + w;
-                const int arow = row0 + rr;
-                const int brow = cw0 * 64 + rr;
-                ra[i] = (arow < r1 && kw < nkw) ? A[(int64_t)arow * sa + aw + kw] : 0ull;
-                rb[i] = (brow < nw * 64 && kw < nkw) ? Bt[(int64_t)brow * sbt + kw] : 0ull;
-            }
-        };
-        auto lstore = [&](int buf) {
+        for (int i = 0; i < 4; i++) {
+            const int tr = 16 * (4 * wave + i) + lr;
+            const int arow = min(row0 + tr, r1 - 1);
+            const int brow = min(cw0 * 64 + tr, ncol - 1);
+            pa[i] = A + (int64_t)arow * sa + aw + 2 * lp;
+            pb[i] = Bt + (int64_t)brow * sbt + 2 * lp;
+        }
+        auto dma = [&](int st) {
+            const int buf = st % G2_NBUF;
+            const uint32_t la = __builtin_amdgcn_readfirstlane(g2_lds_addr(&sA[buf][wave * 512]));
+            const uint32_t lb = __builtin_amdgcn_readfirstlane(g2_lds_addr(&sB[buf][wave * 512]));
 #pragma unroll
-            for (int i = 0; i < G2_KC; i++) {
-                const int e = tid + 256 * i;
-                const int rr = e / G2_KC, w = e % G2_KC;
-                *reinterpret_cast<uint64_t *>(&sA[buf][rr * G2_LD + 2 * w]) = ra[i];
-                *reinterpret_cast<uint64_t *>(&sB[buf][rr * G2_LD + 2 * w]) = rb[i];
+            for (int i = 0; i < 4; i++) {
+                g2_dma16(pa[i] + st * G2_KC, la + 1024 * i);
+                g2_dma16(pb[i] + st * G2_KC, lb + 1024 * i);
             }
         };
         v16i acc[4][4];
@@ -211,45 +267,78 @@ __global__ __launch_bounds__(256) void gemm_mfma2_kernel(uint64_t *C, int64_t sc
             for (int b = 0; b < 4; b++)
 #pragma unroll
                 for (int v = 0; v < 16; v++) acc[a][b][v] = 0;
-        __syncthreads();
-        gload(0);
-        lstore(0);
-        __syncthreads();
-        for (int st = 0; st < nstage; st++) {
-            const int buf = st & 1;
-            if (st + 1 < nstage) gload(st + 1);
-            const int kend = min(G2_KC, nkw - st * G2_KC);
-            for (int w = 0; w < kend; w++) {
-                uint32_t wa[4], wb[4];
+        auto compute = [&](int buf) {
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+                v4i xa[4], xb[4];
 #pragma unroll
                 for (int t = 0; t < 4; t++) {
-                    wa[t] = sA[buf][(wm * 128 + t * 32 + li) * G2_LD + 2 * w + lg];
-                    wb[t] = sB[buf][(wn * 128 + t * 32 + li) * G2_LD + 2 * w + lg];
+                    xa[t] = *reinterpret_cast<const v4i *>(&sA[buf][offa[q][t]]);
+                    xb[t] = *reinterpret_cast<const v4i *>(&sB[buf][offb[q][t]]);
                 }
 #pragma unroll
-                for (int s = 0; s < 2; s++) {
-                    v4i fa[4], fb[4];
+                for (int u = 0; u < 4; u++)
 #pragma unroll
-                    for (int t = 0; t < 4; t++)
+                    for (int s = 0; s < 2; s++) {
+                        v4i fa[4], fb[4];
 #pragma unroll
-                        for (int v = 0; v < 4; v++) {
-                            fa[t][v] = (int)(wa[t] >> (4 * s + v));
-                            fb[t][v] = (int)(wb[t] >> (4 * s + v));
-                        }
+                        for (int t = 0; t < 4; t++)
 #pragma unroll
-                    for (int a = 0; a < 4; a++)
+                            for (int v = 0; v < 4; v++) {
+                                fa[t][v] = (int)(((uint32_t)xa[t][u] >> (4 * s + v)) & 0x01010101u);
+                                fb[t][v] = (int)(((uint32_t)xb[t][u] >> (4 * s + v)) & 0x01010101u);
+                            }
 #pragma unroll
-                        for (int b = 0; b < 4; b++)
-                            acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b],
-                                                                             acc[a][b], 0, 0, 0);
+                        for (int a = 0; a < 4; a++)
+#pragma unroll
+                            for (int b = 0; b < 4; b++)
+                                acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b],
+                                                                                 acc[a][b], 0, 0, 0);
+                    }
+            }
+        };
+        __syncthreads();   // the previous tile's last reads are done
+#pragma unroll
+        for (int s = 0; s < G2_NBUF - 1; s++)
+            if (s < nfull) dma(s);
+        for (int st = 0; st < nfull; st++) {
+            // this wave's loads of stage st have landed (those of stage st + 1, 8
+            // instructions, may still be in flight); after the barrier every
+            // wave's have, and buffer (st + 2) % 3 is no longer read
+            if (st + 1 < nfull)
+                asm volatile("s_waitcnt vmcnt(8)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+            else
+                asm volatile("s_waitcnt vmcnt(0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+            if (st + G2_NBUF - 1 < nfull) dma(st + G2_NBUF - 1);
+            compute(st % G2_NBUF);
+        }
+        if (ktail) {
+            // the pipeline is drained (the last full stage waited for vmcnt 0);
+            // wait for every wave to leave the buffer, then stage the tail words
+            // (zero past the end) with ordinary loads into the same slot layout
+            const int buf = nfull % G2_NBUF;
+            __syncthreads();
+            const int kb = nfull * G2_KC;
+            for (int e = tid; e < G2_TM * 4; e += 256) {
+                const int tr = e >> 2, p = e & 3;
+                const int slot = (tr >> 4) * 128 + 2 * g2_slot(tr & 15, p);
+                const int arow = row0 + tr, brow = cw0 * 64 + tr;
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const int kw = kb + 2 * p + h;
+                    sA[buf][slot + h] = (arow < r1 && kw < nkw) ? A[(int64_t)arow * sa + aw + kw] : 0ull;
+                    sB[buf][slot + h] = (brow < ncol && kw < nkw) ? Bt[(int64_t)brow * sbt + kw] : 0ull;
                 }
             }
-            if (st + 1 < nstage) lstore(buf ^ 1);
             __syncthreads();
+            compute(buf);
         }
-        // bit 0 of each sum -> packed words; lane L collects rows L and 64 + L of
-        // the wave's 128 rows, words 0 and 1 of its 128 columns.
-        uint64_t out[2][2] = {{0ull, 0ull}, {0ull, 0ull}};
+        // bit 0 of each sum -> packed words.  A ballot over one accumulator
+        // register gives 32 columns of two rows (lanes 0-31: row rlo, lanes 32-63:
+        // row rlo + 4); each half is written straight into the lane that stores
+        // that row.  Lane L ends up with rows L and 64 + L of the wave's 128 rows,
+        // words 0 and 1 of its 128 columns, every 32-bit half written once.
+        uint32_t ow[2][2][2] = {};
 #pragma unroll
         for (int a = 0; a < 4; a++)
 #pragma unroll
@@ -258,12 +347,16 @@ __global__ __launch_bounds__(256) void gemm_mfma2_kernel(uint64_t *C, int64_t sc
                 for (int v = 0; v < 16; v++) {
                     const uint64_t bal = __ballot(acc[a][b][v] & 1);
                     const int rlo = 32 * (a & 1) + 8 * (v >> 2) + (v & 3);
-                    const int sh = 32 * (b & 1);
-                    const uint64_t flo = (bal & 0xFFFFFFFFull) << sh;
-                    const uint64_t fhi = (bal >> 32) << sh;
-                    if (lane == rlo) out[a >> 1][b >> 1] |= flo;
-                    if (lane == rlo + 4) out[a >> 1][b >> 1] |= fhi;
+                    uint32_t &o = ow[a >> 1][b >> 1][b & 1];
+                    o = g2_writelane(o, (uint32_t)bal, rlo);
+                    o = g2_writelane(o, (uint32_t)(bal >> 32), rlo + 4);
                 }
+        uint64_t out[2][2];
+#pragma unroll
+        for (int h = 0; h < 2; h++)
+#pragma unroll
+            for (int q = 0; q < 2; q++)
+                out[h][q] = (uint64_t)ow[h][q][0] | ((uint64_t)ow[h][q][1] << 32);
 #pragma unroll
         for (int h = 0; h < 2; h++) {
             const int grow = row0 + wm * 128 + h * 64 + lane;
@@ -286,9 +379,10 @@ hipError_t launch_gemm_mfma(uint64_t *C, int64_t sc, const uint64_t *A, int64_t 
     int nkw = (kmax + 63) / 64;
     if (nw <= 0 || nkw <= 0) return hipSuccess;
     // 256 x 256 tiles pay off once the inner dimension is long enough to hide
-    // their larger prologue and epilogue (measured: K >= 8192 on 65536^2 PLS);
-    // shorter products use the 128 x 128 kernel
-    if (nw >= 4 && kmax > 4096) {
+    // their larger prologue and epilogue (measured on the 65536^2 recursion:
+    // K = 4096 runs 8% faster on them, K = 2048 26% slower); shorter products
+    // use the 128 x 128 kernel
+    if (nw >= 4 && kmax > 2048) {
         int64_t tiles = (int64_t)((m + G2_TM - 1) / G2_TM) * ((nw * 64 + G2_TN - 1) / G2_TN);
         int64_t blocks = tiles < 1024 ? tiles : 1024;
         if (blocks >= 8) blocks = blocks / 8 * 8;

@@ -61,7 +61,7 @@ SCHEDS = {
 @pytest.mark.parametrize("m,k,n", [(1, 1, 1), (64, 64, 64), (100, 70, 130), (257, 300, 190),
                                    (512, 1024, 384), (1000, 129, 65), (1000, 700, 1000),
                                    (300, 4000, 300), (2100, 600, 1100), (257, 65, 4096),
-                                   (300, 8200, 300)])
+                                   (300, 8200, 300), (520, 4160, 700), (256, 4608, 256)])
 def test_addmul(variant, m, k, n):
     say(f"[addmul] variant={variant} m={m} k={k} n={n}")
     A = synth.random_half(m, k, 11 + m)
