@@ -191,7 +191,7 @@ def main() -> int:
     value = ops / (ms * 1e-3)
 
     achieved = prof["ops"] / (prof["ms"] * 1e-3) / 1e12 if prof["ms"] > 0 else 0.0
-    roofline = {"bound": "mfma", "kernel": "gemm_mfma_kernel + gemm_mfma2_kernel (int8 MFMA Schur product, 128x128 and 256x256 tiles)",
+    roofline = {"bound": "mfma", "kernel": "gemm_dma_kernel<4> + gemm_dma_kernel<2> (int8 MFMA Schur product, 256x256 and 128x128 tiles)",
                 "achieved": round(achieved, 1), "peak": INT8_MFMA_PEAK_TOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / INT8_MFMA_PEAK_TOPS, 4),
                 "traffic": pmc_traffic(),
