@@ -40,7 +40,6 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 // round-robin over the 8 XCDs), so the operands a group shares stay in that
 // XCD's L2.
 constexpr int G2_KC = 8;
-constexpr int G2_NBUF = 3;
 constexpr int G2_GROUP = 8;                // row tiles walked per column tile
 
 __device__ inline int g2_slot(int r, int p) {
@@ -76,7 +75,7 @@ __device__ inline uint32_t g2_lds_addr(const uint64_t *p) {
 // block tiles, WT = 2 gives 128 x 128.  The block walks its tiles' K stages as
 // one sequence (tile i, stage s), so the loads of the next tile's first stages
 // are in flight while the current tile finishes and writes back.
-template <int WT>
+template <int WT, int NB>
 __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
                                                        const uint64_t *A, int64_t sa, int m,
                                                        RowRange rows, int aw, int w_lo, int nw,
@@ -86,8 +85,8 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
     constexpr int TM = 64 * WT;             // block tile rows = columns
     constexpr int CPW = TM / 64;            // 1 KiB chunks per wave per operand and stage
     constexpr int STAGE = TM * G2_KC;       // words per operand per stage
-    __shared__ __attribute__((aligned(16))) uint64_t sA[G2_NBUF][STAGE];
-    __shared__ __attribute__((aligned(16))) uint64_t sB[G2_NBUF][STAGE];
+    __shared__ __attribute__((aligned(16))) uint64_t sA[NB][STAGE];
+    __shared__ __attribute__((aligned(16))) uint64_t sB[NB][STAGE];
     int r0, r1;
     eval_range(rk, m, rows, r0, r1);
     const int M = r1 - r0;
@@ -167,7 +166,7 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
                 g2_dma16(pb[c] + n_st * G2_KC, lb + 1024 * c);
             }
         }
-        n_buf = n_buf == G2_NBUF - 1 ? 0 : n_buf + 1;
+        n_buf = n_buf == NB - 1 ? 0 : n_buf + 1;
         if (++n_st == nstage) {
             n_st = 0;
             if (++n_i < ntb) cursor_tile();
@@ -205,7 +204,7 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
         }
     };
 #pragma unroll
-    for (int g = 0; g < G2_NBUF - 1; g++)
+    for (int g = 0; g < NB - 1; g++)
         if (g < nsteps) issue_next();
     int g = 0, buf = 0;
     for (int i = 0; i < ntb; i++) {
@@ -215,7 +214,7 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
             for (int b = 0; b < WT; b++)
 #pragma unroll
                 for (int v = 0; v < 16; v++) acc[a][b][v] = 0;
-        for (int st = 0; st < nstage; st++, g++, buf = buf == G2_NBUF - 1 ? 0 : buf + 1) {
+        for (int st = 0; st < nstage; st++, g++, buf = buf == NB - 1 ? 0 : buf + 1) {
             const bool tail_here = ktail && st == nstage - 1;
             const bool next_full = g + 1 < nsteps &&
                                    !(ktail && (st + 1 < nstage ? st + 2 == nstage : nstage == 1));
@@ -239,7 +238,7 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
                     }
                 }
                 __syncthreads();
-            } else if (next_full) {
+            } else if (NB == 3 && next_full) {
                 // this wave's loads of step g have landed (step g + 1's may still
                 // be in flight); after the barrier every wave's have, and every wave
                 // is done with step g - 1, whose buffer step g + 2 reuses
@@ -250,7 +249,7 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
             } else {
                 asm volatile("s_waitcnt vmcnt(0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
             }
-            if (g + G2_NBUF - 1 < nsteps) issue_next();
+            if (g + NB - 1 < nsteps) issue_next();
             compute(buf);
         }
         {
@@ -314,7 +313,7 @@ hipError_t launch_gemm_mfma(uint64_t *C, int64_t sc, const uint64_t *A, int64_t 
         int64_t blocks = tiles < 256 ? tiles : 256;
         if (blocks >= 8) blocks = blocks / 8 * 8;
         if (blocks < 1) blocks = 1;
-        hipLaunchKernelGGL(gemm_dma_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, st, C, sc, A, sa,
+        hipLaunchKernelGGL((gemm_dma_kernel<4, 3>), dim3((unsigned)blocks), dim3(256), 0, st, C, sc, A, sa,
                            m, rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof);
         return hipGetLastError();
     }
@@ -323,7 +322,7 @@ hipError_t launch_gemm_mfma(uint64_t *C, int64_t sc, const uint64_t *A, int64_t 
     int64_t blocks = tiles < 768 ? tiles : 768;
     if (blocks >= 8) blocks = blocks / 8 * 8;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(gemm_dma_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, st, C, sc, A, sa, m,
+    hipLaunchKernelGGL((gemm_dma_kernel<2, 3>), dim3((unsigned)blocks), dim3(256), 0, st, C, sc, A, sa, m,
                        rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof);
     return hipGetLastError();
 }

@@ -166,6 +166,7 @@ __global__ __launch_bounds__(TB_THREADS) void trsm_block_kernel(
     __shared__ Word2 sX[TB_NB * 64];
     __shared__ Word2 sT[256];
     __shared__ uint64_t sInv[TB_NB * 64];
+    __shared__ uint64_t sIT[TB_NB * 256];   // per diagonal block: 16 groups x 16 combinations of its inverse rows
     int r0, r1;
     eval_range(rk, m, rows, r0, r1);
     const int nr = min(r1 - r0, nbmax * 64);
@@ -193,7 +194,10 @@ __global__ __launch_bounds__(TB_THREADS) void trsm_block_kernel(
     for (int st = 0; st < TB_NB; st++) {
         const int c = lower ? st : nb - 1 - st;
         const bool later = lower ? rb > c : rb < c;
-        lw[st] = (have && st < nb && later) ? Lm[(int64_t)(r0 + row) * sl + lw0 + c] : 0ull;
+        // columns past the triangle (a partial last block) are not part of L
+        const int cv = nr - 64 * c;
+        const uint64_t cmask = cv >= 64 ? ~0ull : ((1ull << max(cv, 0)) - 1);
+        lw[st] = (have && st < nb && later) ? Lm[(int64_t)(r0 + row) * sl + lw0 + c] & cmask : 0ull;
     }
     sX[row] = x;
     if (wave < nb) {
@@ -203,16 +207,35 @@ __global__ __launch_bounds__(TB_THREADS) void trsm_block_kernel(
         sInv[row] = stored ? linv_store[(int64_t)P * 64 + lane] : tri_inverse64_row(dg, lane, lower != 0);
     }
     __syncthreads();
+    // tables of each diagonal block's inverse, so that a row below block b can
+    // fold its multipliers through Inv_bb: x_r += L[r][b] X_b(new)
+    // = (L[r][b] Inv_bb) X_b(old), and one table of X_b(old) per step serves the
+    // diagonal solve and the rows below alike
+    for (int e = tid; e < nb * 256; e += TB_THREADS) {
+        const int blk = e >> 8, g = (e >> 4) & 15, idx = e & 15;
+        uint64_t v = 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if ((idx >> u) & 1) v ^= sInv[64 * blk + 4 * g + u];
+        sIT[e] = v;
+    }
+    __syncthreads();
 #pragma unroll
     for (int st = 0; st < TB_NB; st++) {
         if (st >= nb) break;
         const int b = lower ? st : nb - 1 - st;
         const int bn = min(64, nr - 64 * b);
-        // diagonal: X_b <- Inv_bb X_b
+        // the row's multipliers on X_b(old) (independent of X, ahead of the barrier)
+        uint64_t cp = 0;
+        const uint64_t lv = lw[st];
+        if (lv) {
+#pragma unroll
+            for (int g = 0; g < 16; g++) cp ^= sIT[b * 256 + (g << 4) + (int)((lv >> (4 * g)) & 15)];
+        }
         build_tables_k4<TB_TW>(&sX[64 * b].a, bn, 16, &sT[0].a, tid, TB_THREADS);
-        if (rb == b && have) {
-            const uint64_t c = sInv[row];
-            Word2 y = {0ull, 0ull};
+        const uint64_t c = (rb == b && have) ? sInv[row] : cp;
+        if (c) {
+            Word2 y = (rb == b) ? Word2{0ull, 0ull} : sX[row];
 #pragma unroll
             for (int g = 0; g < 16; g++) {
                 const Word2 t = sT[(g << 4) + (int)((c >> (4 * g)) & 15)];
@@ -220,21 +243,8 @@ __global__ __launch_bounds__(TB_THREADS) void trsm_block_kernel(
                 y.b ^= t.b;
             }
             sX[row] = y;
-        }
-        __syncthreads();
-        if (st + 1 == nb) break;
-        // the blocks still to come: x_r += L[r][b] X_b
-        build_tables_k4<TB_TW>(&sX[64 * b].a, bn, 16, &sT[0].a, tid, TB_THREADS);
-        const uint64_t lv = lw[st];
-        if (lv) {
-            Word2 y = sX[row];
-#pragma unroll
-            for (int g = 0; g < 16; g++) {
-                const Word2 t = sT[(g << 4) + (int)((lv >> (4 * g)) & 15)];
-                y.a ^= t.a;
-                y.b ^= t.b;
-            }
-            sX[row] = y;
+        } else if (rb == b && have) {
+            sX[row] = Word2{0ull, 0ull};
         }
         __syncthreads();
     }
