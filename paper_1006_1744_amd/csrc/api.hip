@@ -577,19 +577,19 @@ extern "C" int gf2_rref(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int
     GF2_TRY(hipStreamSynchronize(st));
     if (r < 0 || r > L.rmax) return GF2_E_ARG;
     const int nwx = (n - r + 63) / 64;
-    if (r > 0) {
+    // with no non-pivot column (r == n) R is the pivot pattern alone: nothing to
+    // gather or solve
+    if (r > 0 && nwx > 0) {
         GF2_TRY(launch_zero_rows(Uc, L.su, r, (r + 63) / 64, st));
-        if (nwx > 0) GF2_TRY(launch_zero_rows(Xc, L.sx, r, nwx, st));
+        GF2_TRY(launch_zero_rows(Xc, L.sx, r, nwx, st));
         GF2_TRY(launch_rref_gather(A_pls.words, A_pls.stride, Q, r, n, PM, NM, pp, pn, Uc, L.su,
                                    Xc, L.sx, st));
-        if (nwx > 0) {
-            UpperSolve us;
-            us.ctx = ctx;
-            us.X = Xc; us.sx = L.sx; us.U = Uc; us.su = L.su; us.r = r; us.nwx = nwx;
-            us.rr = (const int32_t *)(base + L.rr); us.Bt = (uint64_t *)(base + L.bt); us.st = st;
-            us.solve(0, (r + 63) / 64 * 64);
-            if (us.err != hipSuccess) return GF2_E_HIP;
-        }
+        UpperSolve us;
+        us.ctx = ctx;
+        us.X = Xc; us.sx = L.sx; us.U = Uc; us.su = L.su; us.r = r; us.nwx = nwx;
+        us.rr = (const int32_t *)(base + L.rr); us.Bt = (uint64_t *)(base + L.bt); us.st = st;
+        us.solve(0, (r + 63) / 64 * 64);
+        if (us.err != hipSuccess) return GF2_E_HIP;
     }
     GF2_TRY(launch_rref_scatter(R_out.words, R_out.stride, m, n, Q, r, NM, pn, Xc, L.sx, st));
     // zero the padding words of R past ceil(n/64)

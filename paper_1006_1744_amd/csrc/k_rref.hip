@@ -92,19 +92,22 @@ __device__ inline void or_bits(uint64_t *row, int off, int cnt, uint64_t v) {
 }
 
 // Row i < r of S (pivot one at Q[i], zeros left of it, the stored bits right of
-// it) compressed by PM into Uc and by NM into Xc.  Uc, Xc zero on entry.
-// blockIdx.y = word column.
-__global__ void rref_gather_kernel(const uint64_t *Ap, int64_t sap, const int32_t *Q, int r,
+// it) compressed by PM into Uc and by NM into Xc.  Uc, Xc zero on entry.  One
+// thread per (row, word), the word index fastest, so neighbouring threads read
+// neighbouring words of a row and OR into neighbouring words of its compact rows.
+__global__ void rref_gather_kernel(const uint64_t *Ap, int64_t sap, const int32_t *Q, int r, int nw,
                                    const uint64_t *PM, const uint64_t *NM, const int32_t *prefP,
                                    const int32_t *prefN, uint64_t *Uc, int64_t su, uint64_t *Xc,
                                    int64_t sx) {
-    const int w = blockIdx.y;
-    const uint64_t pm = PM[w], nm = NM[w];
-    const int cpp = __popcll(pm), cnn = __popcll(nm);
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < r; i += gridDim.x * blockDim.x) {
+    const int64_t total = (int64_t)r * nw;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / nw), w = (int)(e % nw);
         const int q = Q[i];
         const int qw = q >> 6;
         if (w < qw) continue;   // S is zero left of the pivot word
+        const uint64_t pm = PM[w], nm = NM[w];
+        const int cpp = __popcll(pm), cnn = __popcll(nm);
         uint64_t x = Ap[(int64_t)i * sap + w];
         if (w == qw) {
             const int qb = q & 63;
@@ -116,16 +119,19 @@ __global__ void rref_gather_kernel(const uint64_t *Ap, int64_t sap, const int32_
     }
 }
 
-// R[i] = e_{Q[i]} + the solved non-pivot bits scattered by NM; rows >= r zero.
+// R row i: pivot one at Q[i] (i < r) and the solved non-pivot bits spread back
+// by NM; rows >= r are zero.  One thread per (row, word), the word index fastest.
 __global__ void rref_scatter_kernel(uint64_t *R, int64_t sr, int m, const int32_t *Q, int r,
                                     const uint64_t *NM, const int32_t *prefN, const uint64_t *Xc,
-                                    int64_t sx, int nwr) {
-    const int w = blockIdx.y;
-    const uint64_t nm = NM[w];
-    const int cnt = __popcll(nm), off = prefN[w];
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+                                    int64_t sx, int nw) {
+    const int64_t total = (int64_t)m * nw;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / nw), w = (int)(e % nw);
         uint64_t out = 0;
         if (i < r) {
+            const uint64_t nm = NM[w];
+            const int cnt = __popcll(nm), off = prefN[w];
             if (cnt) {
                 const uint64_t *xr = Xc + (int64_t)i * sx;
                 int o = off >> 6, sh = off & 63;
@@ -138,7 +144,6 @@ __global__ void rref_scatter_kernel(uint64_t *R, int64_t sr, int m, const int32_
         }
         R[(int64_t)i * sr + w] = out;
     }
-    (void)nwr;
 }
 
 __global__ void zero_rows_kernel(uint64_t *X, int64_t sx, int rows, int words) {
@@ -179,10 +184,10 @@ hipError_t launch_rref_gather(const uint64_t *Ap, int64_t sap, const int32_t *Q,
                               int64_t sx, hipStream_t st) {
     if (r <= 0) return hipSuccess;
     const int nw = (n + 63) / 64;
-    int bx = (r + 255) / 256;
-    if (bx > 64) bx = 64;
-    hipLaunchKernelGGL(rref_gather_kernel, dim3(bx, nw), dim3(256), 0, st, Ap, sap, Q, r, PM, NM,
-                       prefP, prefN, Uc, su, Xc, sx);
+    int64_t blocks = ((int64_t)r * nw + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(rref_gather_kernel, dim3((unsigned)blocks), dim3(256), 0, st, Ap, sap, Q, r,
+                       nw, PM, NM, prefP, prefN, Uc, su, Xc, sx);
     return hipGetLastError();
 }
 
@@ -191,10 +196,10 @@ hipError_t launch_rref_scatter(uint64_t *R, int64_t sr, int m, int n, const int3
                                int64_t sx, hipStream_t st) {
     const int nw = (n + 63) / 64;
     if (m <= 0 || nw <= 0) return hipSuccess;
-    int bx = (m + 255) / 256;
-    if (bx > 64) bx = 64;
-    hipLaunchKernelGGL(rref_scatter_kernel, dim3(bx, nw), dim3(256), 0, st, R, sr, m, Q, r, NM,
-                       prefN, Xc, sx, nw);
+    int64_t blocks = ((int64_t)m * nw + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(rref_scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, st, R, sr, m, Q, r,
+                       NM, prefN, Xc, sx, nw);
     return hipGetLastError();
 }
 

@@ -147,7 +147,7 @@ def test_pls_4096(seed):
                                       (500, 700, "planted"), (700, 500, "sparse"),
                                       (1, 50, "half"), (50, 1, "half"), (200, 200, "zero"),
                                       (600, 3000, "half"), (1500, 1400, "planted1200"),
-                                      (1300, 4000, "half")])
+                                      (1300, 4000, "half"), (300, 64, "half"), (1000, 640, "half")])
 def test_rref(m, n, kind):
     if kind == "half":
         A = synth.random_half(m, n, m + 2 * n)
