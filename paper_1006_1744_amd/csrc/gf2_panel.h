@@ -115,13 +115,33 @@ struct SearchLds {
     int sOg[LEAF_W];       // first window: original offset of each entry's row
 };
 
+// Row `lane` of L^{-1} for a panel with ru pivots, lane t holding pivot word
+// urow = u[t] and pivot column qv = q[t] (identity past ru); one wave.
+// L (ru x ru, pivot order): L[t][s] is bit q[s] of u[t].  Lane j solves L x = e_j
+// column by column (x ^= L[:, s] where x[s] = 1), then the columns of L^{-1} are
+// transposed into rows.  The pivot columns sit one per lane, so the loop reads
+// them by readlane.  Straight-line and unrolled so that the column ballots,
+// which do not depend on x, can be issued ahead of the substitution chain;
+// columns s >= ru - 1 are empty (no lane below ru passes the test), so every
+// step may run.
+__device__ inline uint64_t panel_linv_row(uint64_t urow, int qv, int ru, int lane) {
+    uint64_t xcol = 1ull << lane;
+#pragma unroll
+    for (int s2 = 0; s2 < 63; s2++) {
+        const int qs = __builtin_amdgcn_readlane(qv, s2);
+        const uint64_t Lcol = __ballot(lane > s2 && lane < ru && ((urow >> qs) & 1ull));
+        xcol ^= ((xcol >> s2) & 1ull) ? Lcol : 0ull;
+    }
+    return transpose64(xcol, lane);
+}
+
 // Search of the panel at word column wc over rows [R, m).  Writes P and Q at
 // the pivot slots R + t, the window rows' and scanned rows' panel words, and
-// *info (r, F, pa, compress, q, u, linv, moved), and L^{-1} also to linv_out
-// (64 words) when given.  Returns r (in every thread).
+// *info (r, F, pa, compress, q, u, moved), and, when want_linv, L^{-1} to
+// info->linv and to linv_out (64 words) when given.  Returns r (in every thread).
 __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, int wc, int R,
                                    int32_t *P, int32_t *Q, PanelInfo *info, SearchLds &S,
-                                   uint64_t *linv_out = nullptr) {
+                                   uint64_t *linv_out = nullptr, bool want_linv = true) {
     uint64_t *sU = S.sU;
     int32_t *sQ = S.sQ;
     int32_t *sPrel = S.sPrel;
@@ -409,27 +429,14 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
             if (lane + 64 < nk) { mv[1 + 2 * (lane + 64)] = pos1; mv[2 + 2 * (lane + 64)] = src1; }
         }
         TR();
-        // L (r x r, pivot order): L[t][s] is bit q[s] of the pivot word sU[t].
-        // Lane j solves L x = e_j column by column (x ^= L[:, s] where x[s] = 1),
-        // then the columns of L^{-1} are transposed into rows.  Identity past r.
-        // The pivot columns sit one per lane, so the loop reads them by readlane.
         const int ru = __builtin_amdgcn_readfirstlane(r);
         const uint64_t urow = lane < ru ? sU[lane] : 0ull;
         const int qv = lane < ru ? sQ[lane] : lane;
-        // Straight-line and unrolled so that the column ballots, which do not
-        // depend on x, can be issued ahead of the substitution chain; columns
-        // s >= r - 1 are empty (no lane below r passes the test), so every step
-        // may run.
-        uint64_t xcol = 1ull << lane;
-#pragma unroll
-        for (int s2 = 0; s2 < 63; s2++) {
-            const int qs = __builtin_amdgcn_readlane(qv, s2);
-            const uint64_t Lcol = __ballot(lane > s2 && lane < ru && ((urow >> qs) & 1ull));
-            xcol ^= ((xcol >> s2) & 1ull) ? Lcol : 0ull;
+        if (want_linv) {
+            const uint64_t lrow = panel_linv_row(urow, qv, ru, lane);
+            info->linv[lane] = lrow;
+            if (linv_out) linv_out[lane] = lrow;
         }
-        const uint64_t lrow = transpose64(xcol, lane);
-        info->linv[lane] = lrow;
-        if (linv_out) linv_out[lane] = lrow;
         info->q[lane] = qv;
         info->u[lane] = urow;
         const uint64_t moved_cols = __ballot(lane < ru && qv != lane);

@@ -7,11 +7,12 @@ namespace gf2 {
 
 __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
     uint64_t *A, int64_t stride, int m, int n, int wc, int32_t *rk, int b, int32_t *P,
-    int32_t *Q, PanelInfo *info, uint64_t *linv_store) {
+    int32_t *Q, PanelInfo *info) {
     __shared__ SearchLds S;
     const int R = rk[b];
-    const int r = panel_search(A, stride, m, n, wc, R, P, Q, info, S,
-                               linv_store ? linv_store + (int64_t)b * 64 : nullptr);
+    // L^{-1} of the panel is left to the post kernel (its last block), off the
+    // search's critical path: nothing reads it before the table update
+    const int r = panel_search(A, stride, m, n, wc, R, P, Q, info, S, nullptr, false);
     if (threadIdx.x == 0) rk[b + 1] = R + r;
 #ifdef GF2_TRACE
     if (threadIdx.x == 0) info->trace[20] = __builtin_amdgcn_s_memrealtime();
@@ -27,14 +28,16 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
 //    SWAP_W word columns of every moved row through LDS (all reads, one
 //    barrier, all writes), and stages the pivot rows' words on [bw_lo, bw_hi)
 //    for the table update that follows from the same copies.
+//  * the last block computes the panel's L^{-1} (info->linv and the per-panel
+//    store) from the pivot words and columns the search recorded.
 constexpr int POST_THREADS = 256;
 constexpr int POST_ROWS = 4;
 constexpr int SWAP_W = 16;
 
 __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
     uint64_t *A, int64_t stride, uint64_t *Ab, int64_t sb, int blk_lo, int blk_hi, int m, int wc,
-    int nwords, const int32_t *rk, int b, const PanelInfo *info, int nfin, uint64_t *Bbuf,
-    int64_t bstride, int bw_lo, int bw_hi) {
+    int nwords, const int32_t *rk, int b, PanelInfo *info, int nfin, uint64_t *Bbuf,
+    int64_t bstride, int bw_lo, int bw_hi, uint64_t *linv_store) {
     __shared__ uint64_t sT[8][256];
     __shared__ uint64_t sU[64];
     __shared__ int32_t sQ[64];
@@ -52,6 +55,15 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
 #endif
     TRP(0);
     const int r = info->r, F = info->F, pa = info->pa, cmp = info->compress;
+    if (blockIdx.x == gridDim.x - 1) {
+        if (tid < 64) {
+            const uint64_t urow = tid < r ? info->u[tid] : 0ull;
+            const uint64_t lrow = panel_linv_row(urow, info->q[tid], __builtin_amdgcn_readfirstlane(r), tid);
+            info->linv[tid] = lrow;
+            if (linv_store) linv_store[(int64_t)b * 64 + tid] = lrow;
+        }
+        return;
+    }
     if ((int)blockIdx.x < nfin) {
         const bool pend = (F < mrem) && (r > pa);
         if (!pend && !cmp) return;
@@ -142,7 +154,7 @@ hipError_t launch_leaf(uint64_t *A, int64_t stride, uint64_t *Ab, int64_t sb, in
                        uint64_t *linv_store, hipStream_t st) {
     PanelInfo *info = reinterpret_cast<PanelInfo *>(infobuf);
     hipLaunchKernelGGL(leaf_search_kernel, dim3(1), dim3(LEAF_THREADS), 0, st, Ab, sb, m, n, wc, rk,
-                       b, P, Q, info, linv_store);
+                       b, P, Q, info);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int nwords = (n + 63) / 64;
@@ -150,9 +162,9 @@ hipError_t launch_leaf(uint64_t *A, int64_t stride, uint64_t *Ab, int64_t sb, in
     if (nfin > 256) nfin = 256;
     if (nfin < 1) nfin = 1;
     int nswap = (nwords + SWAP_W - 1) / SWAP_W;
-    hipLaunchKernelGGL(panel_post_kernel, dim3(nfin + nswap), dim3(POST_THREADS), 0, st, A, stride,
-                       Ab, sb, blk_lo, blk_hi, m, wc, nwords, rk, b, info, nfin, Bbuf, bstride, bw_lo,
-                       bw_hi);
+    hipLaunchKernelGGL(panel_post_kernel, dim3(nfin + nswap + 1), dim3(POST_THREADS), 0, st, A,
+                       stride, Ab, sb, blk_lo, blk_hi, m, wc, nwords, rk, b, info, nfin, Bbuf, bstride,
+                       bw_lo, bw_hi, linv_store);
     return hipGetLastError();
 }
 
