@@ -151,7 +151,9 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
     int &s_far = S.s_far, &s_tab_lo = S.s_tab_lo, &s_tab_hi = S.s_tab_hi, &s_epochs = S.s_epochs;
     int *sOg = S.sOg;
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // wave index made visibly uniform, so that the one-wave sections below are
+    // uniform branches and their loop state stays in scalar registers
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int mrem = m - R;
     const int nc = min(64, n - 64 * wc);
     uint64_t *col = A + (int64_t)R * stride + wc;
@@ -233,7 +235,7 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
                         cc++;
                         continue;
                     }
-                    if (ts + LEAF_W >= mrem) {   // zero in every remaining row
+                    if (tsu + LEAF_W >= mrem) {   // zero in every remaining row
                         cc++;
                         continue;
                     }

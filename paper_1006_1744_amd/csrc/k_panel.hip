@@ -30,8 +30,8 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
 //    for the table update that follows from the same copies.
 //  * the last block computes the panel's L^{-1} (info->linv and the per-panel
 //    store) from the pivot words and columns the search recorded.
-constexpr int POST_THREADS = 256;
-constexpr int POST_ROWS = 4;
+constexpr int POST_THREADS = 1024;
+constexpr int POST_ROWS = 1;
 constexpr int SWAP_W = 16;
 
 __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
