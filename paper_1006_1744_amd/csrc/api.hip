@@ -211,8 +211,12 @@ struct PlsDriver {
                 chk(launch_table_update(Ab, sb, m, wc, rk, wc, wc + 1, wb + nwd, s.k, s.tables, linv,
                                         Bbuf, bstride, cus, st));
         }
-        if (!dry) chk(launch_compress_chain(Ab, sb, m, wb, nwd, rk, buffered ? wb + nwd : stride, st));
-        if (buffered && !dry) chk(launch_copy_rows(A, stride, wb, pbuf, nwd, 0, nwd, rk, wb, m, st));
+        if (!dry) {
+            if (buffered)
+                chk(launch_compress_chain_out(A, stride, pbuf, m, wb, nwd, rk, st));
+            else
+                chk(launch_compress_chain(Ab, sb, m, wb, nwd, rk, stride, st));
+        }
     }
 
     void node(int wb, int nwd) {

@@ -102,6 +102,8 @@ hipError_t launch_compress_shift(uint64_t *A, int64_t stride, int m, int c0, int
 
 // All shifts of an MMPF block of nwd panels at word wb (splits after each panel),
 // innermost first.
+hipError_t launch_compress_chain_out(uint64_t *A, int64_t stride, uint64_t *Ab, int m, int wb,
+                                     int nwd, const int32_t *rk, hipStream_t st);
 hipError_t launch_compress_chain(uint64_t *A, int64_t stride, int m, int wb, int nwd,
                                  const int32_t *rk, int64_t wlim, hipStream_t st);
 

@@ -472,6 +472,41 @@ hipError_t launch_compress_shift(uint64_t *A, int64_t stride, int m, int c0, int
     return hipGetLastError();
 }
 
+// The same chain on a base block held in a contiguous copy (Ab: rows of nwd
+// words, word w of the block at Ab + row * nwd + (w - wb)), followed by the copy
+// of the block's rows [rk[wb], m) back into A: one thread per row.
+__global__ void compress_chain_out_kernel(uint64_t *A, int64_t stride, uint64_t *Ab, int m, int wb,
+                                          int nwd, const int32_t *rk) {
+    const int Re = rk[wb + nwd];
+    bool any = false;
+    for (int p = 0; p + 1 < nwd; p++) {
+        const int r0 = rk[wb + p + 1] - rk[wb + p];
+        if (r0 < 64 && Re > rk[wb + p + 1]) any = true;
+    }
+    for (int i = rk[wb] + blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += gridDim.x * blockDim.x) {
+        uint64_t *row = Ab + (int64_t)i * nwd - wb;
+        if (any)
+            for (int p = nwd - 2; p >= 0; p--) {
+                const int Rp = rk[wb + p], Rm = rk[wb + p + 1];
+                const int r0 = Rm - Rp, r1 = Re - Rm;
+                if (r0 < 64 && r1 > 0 && i >= Rm) shift_row(row, wb + nwd, 64 * (wb + p), 64, r0, r1, i - Rm);
+            }
+        uint64_t *dst = A + (int64_t)i * stride;
+        for (int w = wb; w < wb + nwd; w++) dst[w] = row[w];
+    }
+}
+
+hipError_t launch_compress_chain_out(uint64_t *A, int64_t stride, uint64_t *Ab, int m, int wb,
+                                     int nwd, const int32_t *rk, hipStream_t st) {
+    int blocks = (m + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(compress_chain_out_kernel, dim3(blocks), dim3(256), 0, st, A, stride, Ab, m,
+                       wb, nwd, rk);
+    return hipGetLastError();
+}
+
 hipError_t launch_compress_chain(uint64_t *A, int64_t stride, int m, int wb, int nwd,
                                  const int32_t *rk, int64_t wlim, hipStream_t st) {
     if (nwd < 2) return hipSuccess;
