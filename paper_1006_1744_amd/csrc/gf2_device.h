@@ -133,38 +133,21 @@ __device__ inline void build_group_tables(const uint64_t *rows, int nrows, int k
         __syncthreads();
         return;
     }
-    // k > 4: every (group, word) pair is split into h runs of consecutive
-    // Gray-code indices; a thread keeps the group's k rows of its word in
-    // registers and walks its run, where each step flips one row
-    // (gray(i + 1) = gray(i) ^ (1 << ctz(i + 1))), so one barrier suffices.
-    (void)on;
-    const int npairs = ng * TW;
-    const int h = max(1, nthr / npairs);
-    const int run = (esz + h - 1) / h;
-    for (int unit = tid; unit < npairs * h; unit += nthr) {
-        const int pair = unit % npairs, part = unit / npairs;
-        const int g = pair / TW, w = pair % TW;
-        uint64_t rr[8];
-#pragma unroll
-        for (int u = 0; u < 8; u++) {
-            const int row = g * k + u;
-            rr[u] = (u < k && row < nrows) ? rows[row * TW + w] : 0ull;
-        }
-        const int i0 = part * run, i1 = min(esz, i0 + run);
-        if (i0 >= i1) continue;
-        int gi = i0 ^ (i0 >> 1);
-        uint64_t v = 0;
-#pragma unroll
-        for (int u = 0; u < 8; u++) v ^= ((gi >> u) & 1) ? rr[u] : 0ull;
-        uint64_t *Tg = T + (size_t)g * esz * TW + w;
-        for (int i = i0; i < i1; i++) {
-            Tg[(size_t)gi * TW] = v;
-            const int b = __builtin_ctz((unsigned)(i + 1));
-            gi ^= 1 << b;
-            v ^= rr[b & 7];
-        }
-    }
+    if (on)
+        for (int g = pq; g < ng; g += pstep) T[(size_t)g * esz * TW + wq] = 0ull;
     __syncthreads();
+    for (int l = 0; l < k; l++) {
+        const int half = 1 << l;
+        if (on)
+            for (int p = pq; p < (ng << l); p += pstep) {
+                const int g = p >> l, idx = p & (half - 1);
+                const int row = g * k + l;
+                const uint64_t add = row < nrows ? rows[row * TW + wq] : 0ull;
+                const size_t t0 = ((size_t)g * esz + idx) * TW + wq;
+                T[t0 + (size_t)half * TW] = T[t0] ^ add;
+            }
+        __syncthreads();
+    }
 }
 
 // One row's part of the "compress L" column move of a node at column c0 split
