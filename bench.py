@@ -36,8 +36,8 @@ INT8_MFMA_PEAK_TOPS = 5000.0   # MI355X dense int8 matrix-core peak (TOP/s)
 # passes over one step (FETCH_SIZE, then WRITE_SIZE), each scaled by what the
 # counter reads for a 1 GiB plain copy in the same run (x2 and x1).  Valid only
 # for the kernel source it was taken with (SHA-256 prefix); otherwise null.
-PMC_TRAFFIC = {"source": "paper_1006_1744_amd/csrc/k_mfma.hip", "sha256_16": "10fe1bae6a6cb493",
-               "bytes_per_launch": 72240629,
+PMC_TRAFFIC = {"source": "paper_1006_1744_amd/csrc/k_mfma.hip", "sha256_16": "4807054f71709f5f",
+               "bytes_per_launch": 72240753,
                "profile": "profiles/gemm_mfma_traffic_65536.md"}
 
 
