@@ -75,6 +75,25 @@ def test_addmul(variant, m, k, n):
     assert np.array_equal(g.to_host(dC), want)
 
 
+@pytest.mark.parametrize("m,k,n", [(4400, 4160, 4160), (20000, 2000, 1000)])
+def test_addmul_multi_tile_sampled(m, k, n):
+    """More tiles than product blocks (each block walks several tiles' stages as
+    one pipeline) with a K tail and partial edge tiles; sampled rows against the
+    oracle's product."""
+    say(f"[addmul sampled] m={m} k={k} n={n}")
+    A = synth.random_half(m, k, 21 + m)
+    B = synth.random_half(k, n, 22 + n)
+    C = synth.random_half(m, n, 23 + k)
+    dC, dA, dB = g.to_device(C), g.to_device(A), g.to_device(B)
+    g.addmul(dC, dA, dB, m, k, n, g.SCHUR_MFMA)
+    torch.cuda.synchronize()
+    got = g.to_host(dC)
+    rows = np.unique(np.concatenate([np.arange(0, m, 97), np.arange(m - 40, m)]))
+    want = oracle.pack_bits(oracle.unpack_bits(C[rows], n) ^ oracle.gf2_matmul_bits(
+        oracle.unpack_bits(A[rows], k), oracle.unpack_bits(B, n)))
+    assert np.array_equal(got[rows][:, :want.shape[1]], want)
+
+
 # ---------------------------------------------------------------- PLS
 SHAPES = [(1, 1), (1, 100), (100, 1), (64, 64), (65, 63), (63, 130), (130, 200), (300, 257),
           (257, 300), (512, 512), (700, 1000), (1000, 700)]
