@@ -210,60 +210,66 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
             int tt = __builtin_amdgcn_readfirstlane(t);
             const int tsu = __builtin_amdgcn_readfirstlane(ts);
             int brk = 0;
-            while (cc < nc && tt < mrem) {
-                const uint64_t b0 = readlane64(c0, cc) & m0;
-                const uint64_t b1 = readlane64(c1, cc) & m1;
-                const int es = tt - tsu;   // < 64: pivots fill the window from its start
-                if (!b0) {
-                    if (b1) {
-                        // pivot in the second half, at entry 64 + fl (no first-half row
-                        // has a one)
-                        const int fl = __ffsll((unsigned long long)b1) - 1;
-                        const uint64_t E1 = b1 & ~(1ull << fl);
-                        const uint64_t f1 = (lane > cc && ((c1 >> fl) & 1ull)) ? ~0ull : 0ull;
-                        c1 ^= E1 & f1;
-                        const uint64_t d = ((c0 >> es) ^ (c1 >> fl)) & 1ull;
-                        c0 ^= d << es;
-                        c1 ^= d << fl;
-                        const int ogs = __builtin_amdgcn_readlane(og0, es);
-                        const int oge = __builtin_amdgcn_readlane(og1, fl);
-                        og0 = lane == es ? oge : og0;
-                        og1 = lane == fl ? ogs : og1;
-                        fer = lane == cc ? 64 + fl : fer;
-                        m0 &= ~(1ull << es);
-                        tt++;
-                        cc++;
-                        continue;
-                    }
-                    if (tsu + LEAF_W >= mrem) {   // zero in every remaining row
-                        cc++;
-                        continue;
-                    }
-                    brk = 1;
-                    break;
+            while (true) {
+                // Common case, kept in a loop of its own with one path: the pivot
+                // of column cc lies in the first half, at entry fl >= es.  Rows
+                // with a one in column cc other than the pivot add the pivot row
+                // on the columns right of cc (column j > cc flips them where the
+                // pivot has a one); then entries es and fl trade places (no change
+                // when fl == es).
+                while (cc < nc && tt < mrem) {
+                    const uint64_t b0 = readlane64(c0, cc) & m0;
+                    if (!b0) break;
+                    const uint64_t b1 = readlane64(c1, cc) & m1;
+                    const int es = tt - tsu;   // < 64: pivots fill the window from its start
+                    const int fl = __ffsll((unsigned long long)b0) - 1;
+                    const uint64_t E0 = b0 & ~(1ull << fl);
+                    // all-ones in lanes j > cc whose pivot bit is set (arithmetic,
+                    // not a select)
+                    const uint32_t f32 =
+                        0u - ((uint32_t)(c0 >> fl) & ((uint32_t)(cc - lane) >> 31) & 1u);
+                    const uint64_t f0 = ((uint64_t)f32 << 32) | f32;
+                    c0 ^= E0 & f0;
+                    c1 ^= b1 & f0;
+                    const uint64_t d = ((c0 >> es) ^ (c0 >> fl)) & 1ull;
+                    c0 ^= (d << es) | (d << fl);
+                    const int ogs = __builtin_amdgcn_readlane(og0, es);
+                    const int oge = __builtin_amdgcn_readlane(og0, fl);
+                    og0 = lane == es ? oge : (lane == fl ? ogs : og0);
+                    fer = lane == cc ? fl : fer;
+                    m0 &= ~(1ull << es);
+                    tt++;
+                    cc++;
                 }
-                // Pivot in the first half, at entry fl >= es (the common case, kept
-                // free of branches).  Rows with a one in column cc other than the
-                // pivot add the pivot row on the columns right of cc: column j > cc
-                // flips them where the pivot has a one.  Then entries es and fl
-                // trade places (no change when fl == es).
-                const int fl = __ffsll((unsigned long long)b0) - 1;
-                const uint64_t E0 = b0 & ~(1ull << fl);
-                // all-ones in lanes j > cc whose pivot bit is set (arithmetic, not a
-                // select, so each half is one three-input bit operation)
-                const uint32_t f32 = 0u - ((uint32_t)(c0 >> fl) & ((uint32_t)(cc - lane) >> 31) & 1u);
-                const uint64_t f0 = ((uint64_t)f32 << 32) | f32;
-                c0 ^= E0 & f0;
-                c1 ^= b1 & f0;
-                const uint64_t d = ((c0 >> es) ^ (c0 >> fl)) & 1ull;
-                c0 ^= (d << es) | (d << fl);
-                const int ogs = __builtin_amdgcn_readlane(og0, es);
-                const int oge = __builtin_amdgcn_readlane(og0, fl);
-                og0 = lane == es ? oge : (lane == fl ? ogs : og0);
-                fer = lane == cc ? fl : fer;
-                m0 &= ~(1ull << es);
-                tt++;
-                cc++;
+                if (!(cc < nc && tt < mrem)) break;
+                // no first-half entry has a one in column cc
+                const uint64_t b1 = readlane64(c1, cc) & m1;
+                const int es = tt - tsu;
+                if (b1) {
+                    // pivot in the second half, at entry 64 + fl
+                    const int fl = __ffsll((unsigned long long)b1) - 1;
+                    const uint64_t E1 = b1 & ~(1ull << fl);
+                    const uint64_t f1 = (lane > cc && ((c1 >> fl) & 1ull)) ? ~0ull : 0ull;
+                    c1 ^= E1 & f1;
+                    const uint64_t d = ((c0 >> es) ^ (c1 >> fl)) & 1ull;
+                    c0 ^= d << es;
+                    c1 ^= d << fl;
+                    const int ogs = __builtin_amdgcn_readlane(og0, es);
+                    const int oge = __builtin_amdgcn_readlane(og1, fl);
+                    og0 = lane == es ? oge : og0;
+                    og1 = lane == fl ? ogs : og1;
+                    fer = lane == cc ? 64 + fl : fer;
+                    m0 &= ~(1ull << es);
+                    tt++;
+                    cc++;
+                    continue;
+                }
+                if (tsu + LEAF_W >= mrem) {   // zero in every remaining row
+                    cc++;
+                    continue;
+                }
+                brk = 1;
+                break;
             }
             TR();
             x0 = transpose64(c0, lane);
