@@ -8,6 +8,26 @@
 
 namespace gf2 {
 
+// v_writelane_b32 (the LLVM intrinsic, so that the compiler places the wait
+// states and the lane-select register it needs): the wave-uniform value v
+// replaces lane `lane` of old.
+extern "C" __device__ int gf2_amdgcn_writelane(int v, int lane, int old)
+    __asm("llvm.amdgcn.writelane.i32");
+
+// Three-input bit operations of gfx950 (v_bitop3_b32; the truth table is
+// indexed by (a << 2) | (b << 1) | c), for the forms the compiler leaves as
+// two instructions.  b is wave-uniform (a scalar register).
+__device__ inline uint32_t xor_and_s(uint32_t a, uint32_t b, uint32_t c) {   // a ^ (b & c)
+    uint32_t d;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x78" : "=v"(d) : "v"(a), "s"(b), "v"(c));
+    return d;
+}
+__device__ inline uint32_t xor_or(uint32_t a, uint32_t b, uint32_t c) {      // a ^ (b | c)
+    uint32_t d;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x1e" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
 __device__ inline uint64_t readlane64(uint64_t v, int l) {
     uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
     uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);

@@ -228,15 +228,21 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
                     // not a select)
                     const uint32_t f32 =
                         0u - ((uint32_t)(c0 >> fl) & ((uint32_t)(cc - lane) >> 31) & 1u);
-                    const uint64_t f0 = ((uint64_t)f32 << 32) | f32;
-                    c0 ^= E0 & f0;
-                    c1 ^= b1 & f0;
+                    c0 = ((uint64_t)xor_and_s((uint32_t)(c0 >> 32), (uint32_t)(E0 >> 32), f32) << 32) |
+                         xor_and_s((uint32_t)c0, (uint32_t)E0, f32);
+                    c1 = ((uint64_t)xor_and_s((uint32_t)(c1 >> 32), (uint32_t)(b1 >> 32), f32) << 32) |
+                         xor_and_s((uint32_t)c1, (uint32_t)b1, f32);
                     const uint64_t d = ((c0 >> es) ^ (c0 >> fl)) & 1ull;
-                    c0 ^= (d << es) | (d << fl);
+                    const uint64_t de = d << es, df = d << fl;
+                    c0 = ((uint64_t)xor_or((uint32_t)(c0 >> 32), (uint32_t)(de >> 32), (uint32_t)(df >> 32)) << 32) |
+                         xor_or((uint32_t)c0, (uint32_t)de, (uint32_t)df);
+                    // entries es and fl of the original-row record trade places
+                    // (lane writes; when es == fl both write the same value)
                     const int ogs = __builtin_amdgcn_readlane(og0, es);
                     const int oge = __builtin_amdgcn_readlane(og0, fl);
-                    og0 = lane == es ? oge : (lane == fl ? ogs : og0);
-                    fer = lane == cc ? fl : fer;
+                    og0 = gf2_amdgcn_writelane(oge, es, og0);
+                    og0 = gf2_amdgcn_writelane(ogs, fl, og0);
+                    fer = gf2_amdgcn_writelane(fl, cc, fer);
                     m0 &= ~(1ull << es);
                     tt++;
                     cc++;
