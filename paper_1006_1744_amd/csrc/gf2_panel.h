@@ -217,7 +217,9 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
                 // on the columns right of cc (column j > cc flips them where the
                 // pivot has a one); then entries es and fl trade places (no change
                 // when fl == es).
-                while (cc < nc && tt < mrem) {
+                // cc and tt advance together here, so one bound covers both limits
+                const int lim = min(nc, cc + (mrem - tt));
+                while (cc < lim) {
                     const uint64_t b0 = readlane64(c0, cc) & m0;
                     if (!b0) break;
                     const uint64_t b1 = readlane64(c1, cc) & m1;
