@@ -1,15 +1,16 @@
 """Benchmark: PLS + RREF of a dense random 65536 x 65536 GF(2) matrix on one MI355X.
 
-One step = gf2_pls (recursive PLS, MMPF base case, Schur products on int8 MFMA)
+One step = gf2_pls (recursive PLS, MMPF base case, Schur products on fp4 MFMA)
 followed by gf2_rref on a fresh copy of the input already resident in HBM
 (every step has its own pristine copy, staged before the timed region).
 
 Prints ONE JSON line.  value = GF(2) operations per second, with the
 operation count 2*W, W = m n r - (m + n) r^2 / 2 + r^3 / 3 the classical
 multiply-add count of a rank-r PLS (2 n^3 / 3 for a full-rank square matrix).
-roofline: the dominant kernel (the int8-MFMA Schur product): its algorithmic
+roofline: the dominant kernel (the MFMA Schur product): its algorithmic
 operations 2*M*N*K per launch over its mean launch time, timed with HIP events
-on the launch stream during the timed steps, against the int8 dense MFMA peak.
+on the launch stream during the timed steps, against the dense matrix-core peak
+of the operand type the schedule uses (fp4 by default, int8 on request).
 cpu_baseline: the CPU oracle (Gaussian PLS, Appendix A) timed on a smaller
 matrix of the same kind on this host.
 batched: the batched workload (4096 matrices, m and n log-uniform in
@@ -30,19 +31,23 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-INT8_MFMA_PEAK_TOPS = 5000.0   # MI355X dense int8 matrix-core peak (TOP/s)
+# MI355X dense matrix-core peaks (TOP/s) of the product's operand types
+MFMA_PEAK_TOPS = {1: ("i8", 5000.0), 2: ("fp4", 10100.0)}
 
 # HBM traffic of the product kernel per launch (bytes), from two rocprofv3 PMC
 # passes over one step (FETCH_SIZE, then WRITE_SIZE), each scaled by what the
 # counter reads for a 1 GiB plain copy in the same run (x2 and x1).  Valid only
-# for the kernel source it was taken with (SHA-256 prefix); otherwise null.
-PMC_TRAFFIC = {"source": "paper_1006_1744_amd/csrc/k_mfma.hip", "sha256_16": "4807054f71709f5f",
-               "bytes_per_launch": 72240753,
+# for the kernel source and operand type it was taken with (SHA-256 prefix,
+# schur code); otherwise null.
+PMC_TRAFFIC = {"source": "paper_1006_1744_amd/csrc/k_mfma.hip", "sha256_16": "unmeasured",
+               "schur": 2, "bytes_per_launch": None,
                "profile": "profiles/gemm_mfma_traffic_65536.md"}
 
 
-def pmc_traffic():
+def pmc_traffic(schur: int):
     import hashlib
+    if schur != PMC_TRAFFIC["schur"]:
+        return None
     path = os.path.join(ROOT, PMC_TRAFFIC["source"])
     with open(path, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest()[:16] != PMC_TRAFFIC["sha256_16"]:
@@ -191,10 +196,16 @@ def main() -> int:
     value = ops / (ms * 1e-3)
 
     achieved = prof["ops"] / (prof["ms"] * 1e-3) / 1e12 if prof["ms"] > 0 else 0.0
-    roofline = {"bound": "mfma", "kernel": "gemm_dma_kernel<4> + gemm_dma_kernel<2> (int8 MFMA Schur product, 256x256 and 128x128 tiles)",
-                "achieved": round(achieved, 1), "peak": INT8_MFMA_PEAK_TOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / INT8_MFMA_PEAK_TOPS, 4),
-                "traffic": pmc_traffic(),
+    schur = (s if s is not None else g.default_sched()).schur
+    if schur not in MFMA_PEAK_TOPS:
+        sys.exit("bench.py: the roofline is defined for the MFMA Schur products (schur 1 or 2)")
+    op_type, peak = MFMA_PEAK_TOPS[schur]
+    roofline = {"bound": "mfma",
+                "kernel": f"gemm_dma_kernel<4> + gemm_dma_kernel<2> ({op_type} MFMA Schur product, "
+                          "256x256 and 128x128 tiles)",
+                "achieved": round(achieved, 1), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": pmc_traffic(schur),
                 "alg_bytes_per_launch": round(alg_bytes / max(len(launches), 1)),
                 "launches_per_step": prof["launches"] // max(args.steps, 1),
                 "mean_launch_us": round(prof["ms"] * 1e3 / max(prof["launches"], 1), 2),
@@ -202,7 +213,7 @@ def main() -> int:
     out = {"metric": "PLS+RREF of a dense random 65536x65536 GF(2) matrix (GF(2) ops/s)",
            "value": value, "unit": "GF(2) ops/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "u64/i8",
+           "scaling": "weak", "vs_baseline": None, "dtype": f"u64/{op_type}",
            "data": "synthetic",
            "config": {"workload": f"PLS + RREF, {m}x{n} iid Bernoulli(1/2), seed {args.seed}",
                       "m": m, "n": n, "rank": r,

@@ -56,7 +56,9 @@ typedef struct gf2_mat {
 
 /* Schur-update variants for the recursive PLS (Section 5: A_SE <- A_SE + A_SW A_NE). */
 enum { GF2_SCHUR_XOR = 0,   /* AND / XOR-popcount on the vector ALUs              */
-       GF2_SCHUR_MFMA = 1   /* int8 MFMA, int32 accumulation, reduced mod 2       */ };
+       GF2_SCHUR_MFMA = 1,  /* int8 MFMA, int32 accumulation, reduced mod 2       */
+       GF2_SCHUR_FP4 = 2    /* fp4 (e2m1) MFMA, fp32 accumulation of exact 0/1
+                               products, reduced mod 2                            */ };
 
 /*
  * Schedule.  Changes timing only, never a result bit.
@@ -66,7 +68,7 @@ enum { GF2_SCHUR_XOR = 0,   /* AND / XOR-popcount on the vector ALUs            
  *  cutoff  recursion cutoff in columns (Section 6): column blocks of at most
  *          `cutoff` columns are factored by the MMPF base case.  Multiple of 64,
  *          64..2^30.  cutoff >= n runs MMPF alone.
- *  schur   GF2_SCHUR_XOR or GF2_SCHUR_MFMA.
+ *  schur   GF2_SCHUR_XOR, GF2_SCHUR_MFMA or GF2_SCHUR_FP4.
  */
 typedef struct gf2_sched {
     int32_t k;
@@ -82,7 +84,8 @@ void gf2_ctx_destroy(gf2_ctx *ctx);
 /* Human-readable name of a status code (static storage). */
 const char *gf2_status_str(int status);
 
-/* The fixed default schedule, the fallback of any tuned or learned choice. */
+/* The fixed default schedule (k 8, tables 8, cutoff 512, GF2_SCHUR_FP4), the
+ * fallback of any tuned or learned choice. */
 void gf2_default_sched(gf2_sched *out);
 
 /* Non-zero if `s` is a valid schedule. */
@@ -168,7 +171,7 @@ int gf2_pls_batched(gf2_ctx *ctx, const gf2_batch_item *items, int64_t count, in
  * Autotuner (schedules only; a schedule never changes a result bit).
  * gf2_sched_candidates: the deduplicated candidate schedules for an m x n
  *   problem: k in 4..8 x tables in {1,2,4,8} x cutoff in {256,512,1024,2048,4096}
- *   x schur in {XOR, MFMA}, where all cutoffs at or above the padded width
+ *   x schur in {XOR, MFMA, FP4}, where all cutoffs at or above the padded width
  *   collapse into one MMPF-only candidate (no Schur product is formed); with
  *   batched != 0, k x tables only (the batched call ignores cutoff and schur).
  *   Writes up to max entries (host array) and returns the total count, or a
@@ -241,8 +244,9 @@ size_t gf2_addmul_workspace_bytes(int64_t m, int64_t k, int64_t n);
  * GF(2) matrix product accumulate C <- C + A * B, the Schur-complement update
  * of Section 5 (A_SE <- A_SE + A_SW * A_NE), exposed for direct use and tests.
  * A is m x k, B is k x n, C is m x n, all device matrices with their own
- * strides; C must not overlap A or B.  `variant` is GF2_SCHUR_XOR or
- * GF2_SCHUR_MFMA; both give identical bits.
+ * strides; C must not overlap A or B.  `variant` is GF2_SCHUR_XOR,
+ * GF2_SCHUR_MFMA or GF2_SCHUR_FP4; all give identical bits; any other value
+ * returns GF2_E_ARG.
  */
 int gf2_addmul(gf2_ctx *ctx, gf2_mat C, gf2_mat A, gf2_mat B, int variant,
                void *ws, size_t ws_bytes, void *stream);

@@ -18,10 +18,11 @@ import torch
 from .build import LIB as _LIB_PATH
 
 __all__ = ["Sched", "Mat", "get_lib", "default_sched", "pls", "rref", "addmul", "to_device",
-           "to_host", "workspace", "Batch", "SCHUR_XOR", "SCHUR_MFMA", "GF2Error"]
+           "to_host", "workspace", "Batch", "SCHUR_XOR", "SCHUR_MFMA", "SCHUR_FP4", "GF2Error"]
 
 SCHUR_XOR = 0
 SCHUR_MFMA = 1
+SCHUR_FP4 = 2
 
 
 class GF2Error(RuntimeError):
@@ -170,7 +171,7 @@ def default_sched() -> Sched:
     return s
 
 
-def sched(k=8, tables=8, cutoff=512, schur=SCHUR_MFMA) -> Sched:
+def sched(k=8, tables=8, cutoff=512, schur=SCHUR_FP4) -> Sched:
     return Sched(k, tables, cutoff, schur)
 
 
@@ -434,7 +435,7 @@ def rref(A_pls: torch.Tensor, m: int, n: int, Q: torch.Tensor, rank: torch.Tenso
 
 
 def addmul(C: torch.Tensor, A: torch.Tensor, B: torch.Tensor, m: int, k: int, n: int,
-           variant: int = SCHUR_MFMA, ws: torch.Tensor | None = None, stream=None):
+           variant: int = SCHUR_FP4, ws: torch.Tensor | None = None, stream=None):
     """C <- C + A * B over GF(2) (A m x k, B k x n, C m x n)."""
     dev = C.device
     nb = int(get_lib().gf2_addmul_workspace_bytes(m, k, n))

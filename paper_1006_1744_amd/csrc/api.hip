@@ -48,7 +48,7 @@ using namespace gf2;
 namespace {
 
 constexpr int64_t kMaxDim = (int64_t)1 << 30;
-constexpr int kMfmaMaxK = 65536;   // int32 sums of +-128*128 products stay exact
+constexpr int kMfmaMaxK = 65536;   // sums of 0/1 products: exact in int32 and in fp32 (< 2^24)
 constexpr int kINF = 0x3fffffff;
 constexpr int kBufWords = 16;       // widest base block worked on in a contiguous copy
 
@@ -59,7 +59,8 @@ bool sched_ok(const gf2_sched *s) {
     if (s->k < 4 || s->k > 8) return false;
     if (s->tables != 1 && s->tables != 2 && s->tables != 4 && s->tables != 8) return false;
     if (s->cutoff < 64 || (s->cutoff % 64) != 0) return false;
-    if (s->schur != GF2_SCHUR_XOR && s->schur != GF2_SCHUR_MFMA) return false;
+    if (s->schur != GF2_SCHUR_XOR && s->schur != GF2_SCHUR_MFMA && s->schur != GF2_SCHUR_FP4)
+        return false;
     return true;
 }
 
@@ -68,7 +69,7 @@ gf2_sched default_sched() {
     s.k = 8;
     s.tables = 8;
     s.cutoff = 512;
-    s.schur = GF2_SCHUR_MFMA;
+    s.schur = GF2_SCHUR_FP4;
     return s;
 }
 
@@ -108,9 +109,9 @@ hipError_t enqueue_gemm(gf2_ctx *ctx, uint64_t *C, int64_t sc, const uint64_t *A
             plog = ctx->plog + 2 * rec.slot;
             if ((e = hipEventRecord(rec.a, st)) != hipSuccess) return e;
         }
-        if (schur == GF2_SCHUR_MFMA)
+        if (schur == GF2_SCHUR_MFMA || schur == GF2_SCHUR_FP4)
             e = launch_gemm_mfma(C, sc, Am, sa, m, crows, aw + k0 / 64, cw, nw, Bt, sbt, kc, br,
-                                 kmrows, rk, plog, st);
+                                 kmrows, rk, plog, schur == GF2_SCHUR_FP4, st);
         else
             e = launch_gemm_xor(C, sc, Am, sa, m, crows, aw + k0 / 64, cw, nw, Bt, sbt, kc, br,
                                 kmrows, rk, plog, st);
@@ -620,7 +621,8 @@ int gf2_addmul(gf2_ctx *ctx, gf2_mat C, gf2_mat A, gf2_mat B, int variant, void 
     if ((rc = check_mat(A)) != GF2_OK) return rc;
     if ((rc = check_mat(B)) != GF2_OK) return rc;
     if (A.m != C.m || B.n != C.n || A.n != B.m) return GF2_E_ARG;
-    if (variant != GF2_SCHUR_XOR && variant != GF2_SCHUR_MFMA) return GF2_E_ARG;
+    if (variant != GF2_SCHUR_XOR && variant != GF2_SCHUR_MFMA && variant != GF2_SCHUR_FP4)
+        return GF2_E_ARG;
     size_t need = gf2_addmul_workspace_bytes(C.m, A.n, C.n);
     if (!ws || ws_bytes < need) return GF2_E_WORKSPACE;
     if (((uintptr_t)ws & 255) != 0) return GF2_E_ALIGN;
@@ -639,9 +641,9 @@ int gf2_addmul(gf2_ctx *ctx, gf2_mat C, gf2_mat A, gf2_mat B, int variant, void 
         const int64_t sbt = (kc + 63) / 64;
         GF2_TRY(launch_transpose(B.words, B.stride, K, br, 0, nw, kc, Bt, sbt, rk, st));
         RowRange cr = row_range(-1, -1, 0, kINF);
-        if (variant == GF2_SCHUR_MFMA)
+        if (variant == GF2_SCHUR_MFMA || variant == GF2_SCHUR_FP4)
             GF2_TRY(launch_gemm_mfma(C.words, C.stride, A.words, A.stride, m, cr, k0 / 64, 0, nw, Bt,
-                                     sbt, kc, br, K, rk, nullptr, st));
+                                     sbt, kc, br, K, rk, nullptr, variant == GF2_SCHUR_FP4, st));
         else
             GF2_TRY(launch_gemm_xor(C.words, C.stride, A.words, A.stride, m, cr, k0 / 64, 0, nw, Bt,
                                     sbt, kc, br, K, rk, nullptr, st));

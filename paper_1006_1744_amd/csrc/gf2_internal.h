@@ -129,7 +129,7 @@ hipError_t launch_gemm_xor(uint64_t *C, int64_t sc, const uint64_t *A, int64_t s
 hipError_t launch_gemm_mfma(uint64_t *C, int64_t sc, const uint64_t *A, int64_t sa, int m,
                             RowRange rows, int aw, int w_lo, int nw, const uint64_t *Bt,
                             int64_t sbt, int kmax, RowRange krows, int kmrows, const int32_t *rk,
-                            int32_t *prof, hipStream_t st);
+                            int32_t *prof, bool fp4, hipStream_t st);
 
 // RREF helpers (k_rref.hip)
 hipError_t launch_zero_rows(uint64_t *X, int64_t sx, int rows, int words, hipStream_t st);

@@ -1,21 +1,27 @@
 // Variant M of the GF(2) product C <- C + A * Bt^T (both operands packed along
-// K): int8 matrix cores (v_mfma_i32_32x32x32_i8), int32 accumulation, result
-// reduced mod 2.
+// K) on the matrix cores, result reduced mod 2, with one of two operand types:
+//  * fp4 (e2m1), v_mfma_scale_f32_32x32x64_f8f6f4 with unit block scales, fp32
+//    accumulation: 64 K-bits per instruction, twice the int8 rate (the default);
+//  * int8, v_mfma_i32_32x32x32_i8, int32 accumulation: 32 K-bits per instruction.
 //
-// Exactness.  Only the parity of the int32 sum is kept.  For integers a, b the
-// product's parity is (a mod 2)(b mod 2), so every operand byte only has to
-// carry the wanted bit in its least significant position.  A lane's 32 K-bits w
-// therefore become two 16-byte MFMA operands: register v of step s is
-// (w >> (4 s + v)) & 0x01010101, whose byte t is bit 8 t + 4 s + v of w.  Both
-// operands use the same (lane group, byte) -> K mapping, so the hardware sums
-// each of the 64 K-bits of a word exactly once.  Sums stay below K <= 65536 per
-// call, far from int32 overflow.
+// Exactness.  Only the parity of each sum is kept.  Every operand element is 0
+// or 1 (the bit itself), so every product is 0 or 1 and each sum is the exact
+// count of matching bit pairs: integers in int32, and in fp32 integers below
+// 2^24 (K <= 65536 per call) with exact rounding-free sums.  A lane's 32
+// K-bits w become operand elements by shifts and masks, with the same (lane
+// group, register, element) -> K mapping on both operands, so the hardware
+// sums each of the 64 K-bits of a word exactly once:
+//  * int8: two 16-byte operands per 32 bits, register v of step s being
+//    (w >> (4 s + v)) & 0x01010101, whose byte t is bit 8 t + 4 s + v of w;
+//  * fp4: one 16-byte operand per 32 bits, register v holding bit 4 n + v of w
+//    in nibble n, placed on the nibble's bit 1 (e2m1 1.0).
 //
-// The mask is not needed for the parity (bits above a byte's LSB never reach
-// the LSB of a product) but for the clock: the matrix cores' power grows with
-// the number of toggling operand bits, and with 0/1 bytes the chip holds a
-// markedly higher clock under this load than with random bytes (measured on
-// 32768^3: about 2.26 GHz against 1.76 GHz, 3.7 against 3.1 POP/s).
+// 0/1 elements are also what keeps the clock up: the matrix cores' power grows
+// with the number of toggling operand bits, and with 0/1 bytes the chip holds a
+// markedly higher clock under the int8 product than with random bytes (measured
+// on 32768^3: about 2.26 GHz against 1.76 GHz, 3.7 against 3.1 POP/s).
+
+#include <type_traits>
 
 #include "gf2_device.h"
 #include "gf2_internal.h"
@@ -23,7 +29,23 @@
 namespace gf2 {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// fp4 (e2m1) operand of v_mfma_scale_f32_32x32x64_f8f6f4 from a lane's 32
+// K-bits w: register v holds bit 4 n + v of w as nibble n (n = 0..7), on the
+// nibble's bit 1, so a set bit reads as e2m1 1.0 (exponent 01, mantissa 0) and
+// a clear one as 0.  The block scales are 127 (2^0) on both sides.
+__device__ inline v8i g2_fp4(uint32_t w) {
+    v8i f;
+    f[0] = (int)((w << 1) & 0x22222222u);
+    f[1] = (int)(w & 0x22222222u);
+    f[2] = (int)((w >> 1) & 0x22222222u);
+    f[3] = (int)((w >> 2) & 0x22222222u);
+    f[4] = f[5] = f[6] = f[7] = 0;   // unused by fp4 operands
+    return f;
+}
 
 // Block tiles of 256 x 256 (4 x 4 MFMA tiles of 32 x 32 per wave, 256
 // accumulators) or 128 x 128 (2 x 2 per wave), 2 x 2 waves, fed by direct
@@ -71,7 +93,7 @@ __device__ inline uint32_t g2_lds_addr(const uint64_t *p) {
 // block tiles, WT = 2 gives 128 x 128.  The block walks its tiles' K stages as
 // one sequence (tile i, stage s), so the loads of the next tile's first stages
 // are in flight while the current tile finishes and writes back.
-template <int WT, int NB>
+template <int WT, int NB, bool F4>
 __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
                                                        const uint64_t *A, int64_t sa, int m,
                                                        RowRange rows, int aw, int w_lo, int nw,
@@ -168,7 +190,8 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
             if (++n_i < ntb) cursor_tile();
         }
     };
-    v16i acc[WT][WT];
+    typedef typename std::conditional<F4, v16f, v16i>::type acc_t;
+    acc_t acc[WT][WT];
     auto compute = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < 2; q++) {
@@ -178,25 +201,45 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
                 xa[t] = *reinterpret_cast<const v4i *>(&sA[buf][offa[q][t]]);
                 xb[t] = *reinterpret_cast<const v4i *>(&sB[buf][offb[q][t]]);
             }
+            if constexpr (F4) {
+                // one fp4 MFMA (64 K-bits over both lane groups) per 32-bit part
 #pragma unroll
-            for (int u = 0; u < 4; u++)
+                for (int u = 0; u < 4; u++) {
+                    v8i fa[WT], fb[WT];
 #pragma unroll
-                for (int s = 0; s < 2; s++) {
-                    v4i fa[WT], fb[WT];
-#pragma unroll
-                    for (int t = 0; t < WT; t++)
-#pragma unroll
-                        for (int v = 0; v < 4; v++) {
-                            fa[t][v] = (int)(((uint32_t)xa[t][u] >> (4 * s + v)) & 0x01010101u);
-                            fb[t][v] = (int)(((uint32_t)xb[t][u] >> (4 * s + v)) & 0x01010101u);
-                        }
+                    for (int t = 0; t < WT; t++) {
+                        fa[t] = g2_fp4((uint32_t)xa[t][u]);
+                        fb[t] = g2_fp4((uint32_t)xb[t][u]);
+                    }
 #pragma unroll
                     for (int a = 0; a < WT; a++)
 #pragma unroll
                         for (int b = 0; b < WT; b++)
-                            acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b],
-                                                                             acc[a][b], 0, 0, 0);
+                            acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                                fa[a], fb[b], acc[a][b], 4, 4, 0, 127, 0, 127);
                 }
+            } else {
+                // two int8 MFMAs (32 K-bits each) per 32-bit part
+#pragma unroll
+                for (int u = 0; u < 4; u++)
+#pragma unroll
+                    for (int s = 0; s < 2; s++) {
+                        v4i fa[WT], fb[WT];
+#pragma unroll
+                        for (int t = 0; t < WT; t++)
+#pragma unroll
+                            for (int v = 0; v < 4; v++) {
+                                fa[t][v] = (int)(((uint32_t)xa[t][u] >> (4 * s + v)) & 0x01010101u);
+                                fb[t][v] = (int)(((uint32_t)xb[t][u] >> (4 * s + v)) & 0x01010101u);
+                            }
+#pragma unroll
+                        for (int a = 0; a < WT; a++)
+#pragma unroll
+                            for (int b = 0; b < WT; b++)
+                                acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b],
+                                                                                 acc[a][b], 0, 0, 0);
+                    }
+            }
         }
     };
 #pragma unroll
@@ -209,7 +252,11 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
 #pragma unroll
             for (int b = 0; b < WT; b++)
 #pragma unroll
-                for (int v = 0; v < 16; v++) acc[a][b][v] = 0;
+                for (int v = 0; v < 16; v++) {
+                    // one matrix-register write per element (a float zero vector
+                    // would otherwise be kept in spare matrix registers and copied)
+                    asm volatile("v_accvgpr_write_b32 %0, 0" : "=a"(acc[a][b][v]));
+                }
         for (int st = 0; st < nstage; st++, g++, buf = buf == NB - 1 ? 0 : buf + 1) {
             const bool tail_here = ktail && st == nstage - 1;
             const bool next_full = g + 1 < nsteps &&
@@ -268,6 +315,7 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
                         // compiler copies all 256 out at once, which spills)
                         int x;
                         asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(x) : "a"(acc[a][b][v]));
+                        if constexpr (F4) x = (int)__builtin_bit_cast(float, x);   // exact count
                         const uint64_t bal = __ballot(x & 1);
                         const int rlo = 32 * (a & 1) + 8 * (v >> 2) + (v & 3);
                         uint32_t &o = ow[a >> 1][b >> 1][b & 1];
@@ -296,7 +344,7 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
 hipError_t launch_gemm_mfma(uint64_t *C, int64_t sc, const uint64_t *A, int64_t sa, int m,
                             RowRange rows, int aw, int w_lo, int nw, const uint64_t *Bt,
                             int64_t sbt, int kmax, RowRange krows, int kmrows, const int32_t *rk,
-                            int32_t *prof, hipStream_t st) {
+                            int32_t *prof, bool fp4, hipStream_t st) {
     int nkw = (kmax + 63) / 64;
     if (nw <= 0 || nkw <= 0) return hipSuccess;
     // 256 x 256 tiles pay off once the inner dimension is long enough to
@@ -309,8 +357,12 @@ hipError_t launch_gemm_mfma(uint64_t *C, int64_t sc, const uint64_t *A, int64_t 
         int64_t blocks = tiles < 256 ? tiles : 256;
         if (blocks >= 8) blocks = blocks / 8 * 8;
         if (blocks < 1) blocks = 1;
-        hipLaunchKernelGGL((gemm_dma_kernel<4, 3>), dim3((unsigned)blocks), dim3(256), 0, st, C, sc, A, sa,
-                           m, rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof);
+        if (fp4)
+            hipLaunchKernelGGL((gemm_dma_kernel<4, 3, true>), dim3((unsigned)blocks), dim3(256), 0, st, C,
+                               sc, A, sa, m, rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof);
+        else
+            hipLaunchKernelGGL((gemm_dma_kernel<4, 3, false>), dim3((unsigned)blocks), dim3(256), 0, st, C,
+                               sc, A, sa, m, rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof);
         return hipGetLastError();
     }
     // three blocks per CU (48 KiB of LDS each)
@@ -318,8 +370,12 @@ hipError_t launch_gemm_mfma(uint64_t *C, int64_t sc, const uint64_t *A, int64_t 
     int64_t blocks = tiles < 768 ? tiles : 768;
     if (blocks >= 8) blocks = blocks / 8 * 8;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((gemm_dma_kernel<2, 3>), dim3((unsigned)blocks), dim3(256), 0, st, C, sc, A, sa, m,
-                       rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof);
+    if (fp4)
+        hipLaunchKernelGGL((gemm_dma_kernel<2, 3, true>), dim3((unsigned)blocks), dim3(256), 0, st, C, sc,
+                           A, sa, m, rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof);
+    else
+        hipLaunchKernelGGL((gemm_dma_kernel<2, 3, false>), dim3((unsigned)blocks), dim3(256), 0, st, C, sc,
+                           A, sa, m, rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof);
     return hipGetLastError();
 }
 

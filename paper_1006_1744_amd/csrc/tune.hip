@@ -56,6 +56,7 @@ int gf2_sched_candidates(int64_t m, int64_t n, int batched, gf2_sched *out, int 
                 }
                 c.push_back({k, t, cut, GF2_SCHUR_XOR});
                 c.push_back({k, t, cut, GF2_SCHUR_MFMA});
+                c.push_back({k, t, cut, GF2_SCHUR_FP4});
             }
         }
     const int cnt = (int)c.size();

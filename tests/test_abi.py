@@ -41,8 +41,10 @@ def test_sched_validation(lib):
     import paper_1006_1744_amd as g
     s = g.default_sched()
     assert lib.gf2_sched_valid(ctypes.byref(s)) == 1
+    for schur in (g.SCHUR_XOR, g.SCHUR_MFMA, g.SCHUR_FP4):
+        assert lib.gf2_sched_valid(ctypes.byref(g.Sched(8, 8, 512, schur))) == 1
     for bad in [g.Sched(3, 8, 512, 1), g.Sched(8, 3, 512, 1), g.Sched(8, 8, 100, 1),
-                g.Sched(8, 8, 512, 2), g.Sched(9, 8, 512, 0)]:
+                g.Sched(8, 8, 512, 3), g.Sched(8, 8, 512, -1), g.Sched(9, 8, 512, 0)]:
         assert lib.gf2_sched_valid(ctypes.byref(bad)) == 0
         assert lib.gf2_pls_workspace_bytes(100, 100, ctypes.byref(bad)) == 0
 
@@ -68,9 +70,9 @@ def test_null_context_rejected(lib):
 
 def test_sched_candidates_counts_and_validity():
     import paper_1006_1744_amd as g
-    for m, n, batched, want in [(100, 100, False, 20), (300, 300, False, 60),
-                                (5000, 5000, False, 200), (64, 4096, False, 180),
-                                (64, 4097, False, 200), (3000, 3000, True, 20)]:
+    for m, n, batched, want in [(100, 100, False, 20), (300, 300, False, 80),
+                                (5000, 5000, False, 300), (64, 4096, False, 260),
+                                (64, 4097, False, 300), (3000, 3000, True, 20)]:
         c = g.sched_candidates(m, n, batched)
         assert len(c) == want
         assert len({x.astuple() for x in c}) == want

@@ -100,14 +100,14 @@ def compare(label, got, want):
     assert np.array_equal(gAp, Ap), f"{label}: A' differs"
 
 
-def test_full_65536_dense_both_schur_variants():
+def test_full_65536_dense_all_schur_variants():
     m = n = 65536
     A = synth.random_half(m, n, 1)
-    say("[full] 65536^2 p=1/2 seed 1: GPU (MFMA Schur, default schedule)")
+    say("[full] 65536^2 p=1/2 seed 1: GPU (fp4 MFMA Schur, default schedule)")
     got = run_full(A, m, n)
     say("[full] oracle")
     want = oracle.pls(A, m, n)
-    compare("65536 MFMA", got, want)
+    compare("65536 fp4 MFMA", got, want)
     r = want[0]
     if r == n:   # full rank: the RREF is the identity
         I = np.zeros_like(got[4])
@@ -116,6 +116,10 @@ def test_full_65536_dense_both_schur_variants():
         assert np.array_equal(got[4], I)
     else:
         check_rref_properties(got[4], s_rows(want[3], r, want[2], n), r, want[2], n)
+    say("[full] GPU with the int8 MFMA Schur product")
+    got_i = run_full(A, m, n, g.Sched(8, 8, 512, g.SCHUR_MFMA), rref=False)
+    compare("65536 int8 MFMA", got_i, want)
+    del got_i
     say("[full] GPU with the XOR-popcount Schur product")
     got_x = run_full(A, m, n, g.Sched(8, 8, 512, g.SCHUR_XOR), rref=False)
     compare("65536 XOR", got_x, want)

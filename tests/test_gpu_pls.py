@@ -53,11 +53,13 @@ SCHEDS = {
     "rec64_mfma": g.Sched(8, 8, 64, g.SCHUR_MFMA),
     "k4t1_c128": g.Sched(4, 1, 128, g.SCHUR_XOR),
     "k5t2_c256": g.Sched(5, 2, 256, g.SCHUR_MFMA),
+    "rec64_fp4": g.Sched(8, 8, 64, g.SCHUR_FP4),
+    "k6t4_c128_fp4": g.Sched(6, 4, 128, g.SCHUR_FP4),
 }
 
 
 # ---------------------------------------------------------------- products
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("m,k,n", [(1, 1, 1), (64, 64, 64), (100, 70, 130), (257, 300, 190),
                                    (512, 1024, 384), (1000, 129, 65), (1000, 700, 1000),
                                    (300, 4000, 300), (2100, 600, 1100), (257, 65, 4096),
@@ -75,17 +77,18 @@ def test_addmul(variant, m, k, n):
     assert np.array_equal(g.to_host(dC), want)
 
 
+@pytest.mark.parametrize("variant", [1, 2])
 @pytest.mark.parametrize("m,k,n", [(4400, 4160, 4160), (20000, 2000, 1000)])
-def test_addmul_multi_tile_sampled(m, k, n):
+def test_addmul_multi_tile_sampled(variant, m, k, n):
     """More tiles than product blocks (each block walks several tiles' stages as
     one pipeline) with a K tail and partial edge tiles; sampled rows against the
     oracle's product."""
-    say(f"[addmul sampled] m={m} k={k} n={n}")
+    say(f"[addmul sampled] variant={variant} m={m} k={k} n={n}")
     A = synth.random_half(m, k, 21 + m)
     B = synth.random_half(k, n, 22 + n)
     C = synth.random_half(m, n, 23 + k)
     dC, dA, dB = g.to_device(C), g.to_device(A), g.to_device(B)
-    g.addmul(dC, dA, dB, m, k, n, g.SCHUR_MFMA)
+    g.addmul(dC, dA, dB, m, k, n, variant)
     torch.cuda.synchronize()
     got = g.to_host(dC)
     rows = np.unique(np.concatenate([np.arange(0, m, 97), np.arange(m - 40, m)]))
@@ -114,7 +117,7 @@ def test_pls_sparse(sname, p, m, n):
     assert_same_pls(A, m, n, SCHEDS[sname], f"p={p}/{sname}")
 
 
-@pytest.mark.parametrize("sname", ["default", "mmpf", "rec64_mfma", "k4t1_c128"])
+@pytest.mark.parametrize("sname", ["default", "mmpf", "rec64_mfma", "k4t1_c128", "rec64_fp4"])
 @pytest.mark.parametrize("m,n,r", [(200, 300, 90), (512, 512, 300), (700, 900, 650),
                                    (1000, 1000, 999), (300, 300, 0), (800, 400, 130)])
 def test_pls_planted(sname, m, n, r):
