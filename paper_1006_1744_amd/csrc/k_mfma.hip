@@ -14,7 +14,7 @@
 //  * int8: two 16-byte operands per 32 bits, register v of step s being
 //    (w >> (4 s + v)) & 0x01010101, whose byte t is bit 8 t + 4 s + v of w;
 //  * fp4: one 16-byte operand per 32 bits, register v holding bit 4 n + v of w
-//    in nibble n, placed on the nibble's bit 1 (e2m1 1.0).
+//    in nibble n, as e2m1 values whose A x B products are exactly 1.
 //
 // 0/1 elements are also what keeps the clock up: the matrix cores' power grows
 // with the number of toggling operand bits, and with 0/1 bytes the chip holds a
@@ -33,17 +33,29 @@ typedef int v8i __attribute__((ext_vector_type(8)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-// fp4 (e2m1) operand of v_mfma_scale_f32_32x32x64_f8f6f4 from a lane's 32
-// K-bits w: register v holds bit 4 n + v of w as nibble n (n = 0..7), on the
-// nibble's bit 1, so a set bit reads as e2m1 1.0 (exponent 01, mantissa 0) and
-// a clear one as 0.  The block scales are 127 (2^0) on both sides.
-__device__ inline v8i g2_fp4(uint32_t w) {
+// fp4 (e2m1) operands of v_mfma_scale_f32_32x32x64_f8f6f4 from a lane's 32
+// K-bits w: register v holds bit 4 n + v of w in nibble n (n = 0..7), on a
+// nibble bit chosen so that each register needs at most one shift.  A set bit
+// reads on the A side as 0.5, 1, 2, 2 (registers 0-3: e2m1 codes 0001, 0010,
+// 0100, 0100) and on the B side as 2, 1, 0.5, 0.5, so every product of two set
+// bits is exactly 1 and a clear bit reads as 0.  The block scales are 127
+// (2^0) on both sides.
+__device__ inline v8i g2_fp4_a(uint32_t w) {
     v8i f;
-    f[0] = (int)((w << 1) & 0x22222222u);
+    f[0] = (int)(w & 0x11111111u);
     f[1] = (int)(w & 0x22222222u);
-    f[2] = (int)((w >> 1) & 0x22222222u);
-    f[3] = (int)((w >> 2) & 0x22222222u);
+    f[2] = (int)(w & 0x44444444u);
+    f[3] = (int)((w >> 1) & 0x44444444u);
     f[4] = f[5] = f[6] = f[7] = 0;   // unused by fp4 operands
+    return f;
+}
+__device__ inline v8i g2_fp4_b(uint32_t w) {
+    v8i f;
+    f[0] = (int)((w << 2) & 0x44444444u);
+    f[1] = (int)(w & 0x22222222u);
+    f[2] = (int)((w >> 2) & 0x11111111u);
+    f[3] = (int)((w >> 3) & 0x11111111u);
+    f[4] = f[5] = f[6] = f[7] = 0;
     return f;
 }
 
@@ -192,60 +204,113 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
     };
     typedef typename std::conditional<F4, v16f, v16i>::type acc_t;
     acc_t acc[WT][WT];
-    auto compute = [&](int buf) {
+    // one round: the MFMAs of the word pairs (xa, xb) a lane read for round q
+    auto compute_round = [&](const v4i *xa, const v4i *xb) {
+        if constexpr (F4) {
+            // one fp4 MFMA (64 K-bits over both lane groups) per 32-bit part
 #pragma unroll
-        for (int q = 0; q < 2; q++) {
-            v4i xa[WT], xb[WT];
+            for (int u = 0; u < 4; u++) {
+                v8i fa[WT], fb[WT];
 #pragma unroll
-            for (int t = 0; t < WT; t++) {
-                xa[t] = *reinterpret_cast<const v4i *>(&sA[buf][offa[q][t]]);
-                xb[t] = *reinterpret_cast<const v4i *>(&sB[buf][offb[q][t]]);
+                for (int t = 0; t < WT; t++) {
+                    fa[t] = g2_fp4_a((uint32_t)xa[t][u]);
+                    fb[t] = g2_fp4_b((uint32_t)xb[t][u]);
+                }
+#pragma unroll
+                for (int a = 0; a < WT; a++)
+#pragma unroll
+                    for (int b = 0; b < WT; b++)
+                        acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                            fa[a], fb[b], acc[a][b], 4, 4, 0, 127, 0, 127);
             }
-            if constexpr (F4) {
-                // one fp4 MFMA (64 K-bits over both lane groups) per 32-bit part
+        } else {
+            // two int8 MFMAs (32 K-bits each) per 32-bit part
 #pragma unroll
-                for (int u = 0; u < 4; u++) {
-                    v8i fa[WT], fb[WT];
+            for (int u = 0; u < 4; u++)
 #pragma unroll
-                    for (int t = 0; t < WT; t++) {
-                        fa[t] = g2_fp4((uint32_t)xa[t][u]);
-                        fb[t] = g2_fp4((uint32_t)xb[t][u]);
-                    }
+                for (int s = 0; s < 2; s++) {
+                    v4i fa[WT], fb[WT];
+#pragma unroll
+                    for (int t = 0; t < WT; t++)
+#pragma unroll
+                        for (int v = 0; v < 4; v++) {
+                            fa[t][v] = (int)(((uint32_t)xa[t][u] >> (4 * s + v)) & 0x01010101u);
+                            fb[t][v] = (int)(((uint32_t)xb[t][u] >> (4 * s + v)) & 0x01010101u);
+                        }
 #pragma unroll
                     for (int a = 0; a < WT; a++)
 #pragma unroll
                         for (int b = 0; b < WT; b++)
-                            acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                                fa[a], fb[b], acc[a][b], 4, 4, 0, 127, 0, 127);
+                            acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b],
+                                                                             acc[a][b], 0, 0, 0);
                 }
-            } else {
-                // two int8 MFMAs (32 K-bits each) per 32-bit part
-#pragma unroll
-                for (int u = 0; u < 4; u++)
-#pragma unroll
-                    for (int s = 0; s < 2; s++) {
-                        v4i fa[WT], fb[WT];
-#pragma unroll
-                        for (int t = 0; t < WT; t++)
-#pragma unroll
-                            for (int v = 0; v < 4; v++) {
-                                fa[t][v] = (int)(((uint32_t)xa[t][u] >> (4 * s + v)) & 0x01010101u);
-                                fb[t][v] = (int)(((uint32_t)xb[t][u] >> (4 * s + v)) & 0x01010101u);
-                            }
-#pragma unroll
-                        for (int a = 0; a < WT; a++)
-#pragma unroll
-                            for (int b = 0; b < WT; b++)
-                                acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b],
-                                                                                 acc[a][b], 0, 0, 0);
-                    }
-            }
         }
     };
+    auto read_round = [&](int b, int q, v4i *xa, v4i *xb) {
 #pragma unroll
-    for (int g = 0; g < NB - 1; g++)
-        if (g < nsteps) issue_next();
-    int g = 0, buf = 0;
+        for (int t = 0; t < WT; t++) {
+            xa[t] = *reinterpret_cast<const v4i *>(&sA[b][offa[q][t]]);
+            xb[t] = *reinterpret_cast<const v4i *>(&sB[b][offb[q][t]]);
+        }
+    };
+    // Make step gn's operands visible to every wave (step gn is stage sn of tile
+    // tn).  Before the call each wave has issued all its LDS reads of step gn - 1
+    // and DMA up to step gn + 1.
+    //  * full stage: this wave's DMA of step gn has landed once at most step
+    //    gn + 1's is in flight; after the barrier every wave's has, and every wave
+    //    has read step gn - 1 (the lgkmcnt wait), so step gn + 2 may reuse its
+    //    buffer.
+    //  * tail stage: drain, then stage the tail words (zero past the end) with
+    //    ordinary loads into the same slot layout; buffer gn % 3 was last read at
+    //    step gn - 3 and no DMA targets it.
+    auto arrive = [&](int gn, int sn, int tn) {
+        const int b = gn % NB;
+        if (ktail && sn == nstage - 1) {
+            asm volatile("s_waitcnt vmcnt(0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+            int row0, cw0;
+            tile_at(tn, row0, cw0);
+            const int kb = nfull * G2_KC;
+            for (int e = tid; e < TM * 4; e += 256) {
+                const int tr = e >> 2, p = e & 3;
+                const int slot = (tr >> 4) * 128 + 2 * g2_slot(tr & 15, p);
+                const int arow = row0 + tr, brow = cw0 * 64 + tr;
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const int kw = kb + 2 * p + h;
+                    sA[b][slot + h] = (arow < r1 && kw < nkw) ? A[(int64_t)arow * sa + aw + kw] : 0ull;
+                    sB[b][slot + h] = (brow < ncol && kw < nkw) ? Bt[(int64_t)brow * sbt + kw] : 0ull;
+                }
+            }
+            __syncthreads();
+            return;
+        }
+        // is step gn + 1 a DMA stage (issued, possibly still in flight)?
+        const bool next_full = gn + 1 < nsteps &&
+                               !(ktail && (sn + 1 < nstage ? sn + 2 == nstage : nstage == 1));
+        if (next_full) {
+            if constexpr (CPW == 4)
+                asm volatile("s_waitcnt vmcnt(8)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+            else
+                asm volatile("s_waitcnt vmcnt(4)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        } else {
+            asm volatile("s_waitcnt vmcnt(0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        }
+    };
+    // Software pipeline over the flat step sequence: step g's round-1 reads are
+    // issued before its round-0 MFMAs, and step g + 1 is made visible (and its
+    // round-0 reads issued) between step g's two rounds, so the LDS latency and
+    // the barrier overlap matrix-core work instead of opening each round.
+    static_assert(NB == 3, "three stages in flight");
+    v4i xa0[WT], xb0[WT], xa1[WT], xb1[WT];
+#pragma unroll
+    for (int gi = 0; gi < NB - 1; gi++)
+        if (gi < nsteps) issue_next();
+    if (nsteps > 0) {
+        arrive(0, 0, 0);
+        if (NB - 1 < nsteps) issue_next();
+        read_round(0, 0, xa0, xb0);
+    }
+    int g = 0;
     for (int i = 0; i < ntb; i++) {
 #pragma unroll
         for (int a = 0; a < WT; a++)
@@ -257,43 +322,23 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
                     // would otherwise be kept in spare matrix registers and copied)
                     asm volatile("v_accvgpr_write_b32 %0, 0" : "=a"(acc[a][b][v]));
                 }
-        for (int st = 0; st < nstage; st++, g++, buf = buf == NB - 1 ? 0 : buf + 1) {
-            const bool tail_here = ktail && st == nstage - 1;
-            const bool next_full = g + 1 < nsteps &&
-                                   !(ktail && (st + 1 < nstage ? st + 2 == nstage : nstage == 1));
-            if (tail_here) {
-                // drain, then stage the tail words (zero past the end) with ordinary
-                // loads into the same slot layout; buffer g % 3 was last read at
-                // step g - 3
-                asm volatile("s_waitcnt vmcnt(0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-                int row0, cw0;
-                tile_at(i, row0, cw0);
-                const int kb = nfull * G2_KC;
-                for (int e = tid; e < TM * 4; e += 256) {
-                    const int tr = e >> 2, p = e & 3;
-                    const int slot = (tr >> 4) * 128 + 2 * g2_slot(tr & 15, p);
-                    const int arow = row0 + tr, brow = cw0 * 64 + tr;
+        for (int st = 0; st < nstage; st++, g++) {
+            read_round(g % NB, 1, xa1, xb1);
+            compute_round(xa0, xb0);
+            // keep round 0's matrix work ahead of the next stage's barrier, so the
+            // next stage's first LDS reads overlap round 1 (left alone, the
+            // compiler sinks round 0 below the barrier)
 #pragma unroll
-                    for (int h = 0; h < 2; h++) {
-                        const int kw = kb + 2 * p + h;
-                        sA[buf][slot + h] = (arow < r1 && kw < nkw) ? A[(int64_t)arow * sa + aw + kw] : 0ull;
-                        sB[buf][slot + h] = (brow < ncol && kw < nkw) ? Bt[(int64_t)brow * sbt + kw] : 0ull;
-                    }
-                }
-                __syncthreads();
-            } else if (NB == 3 && next_full) {
-                // this wave's loads of step g have landed (step g + 1's may still
-                // be in flight); after the barrier every wave's have, and every wave
-                // is done with step g - 1, whose buffer step g + 2 reuses
-                if constexpr (CPW == 4)
-                    asm volatile("s_waitcnt vmcnt(8)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-                else
-                    asm volatile("s_waitcnt vmcnt(4)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-            } else {
-                asm volatile("s_waitcnt vmcnt(0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+            for (int a = 0; a < WT; a++)
+#pragma unroll
+                for (int b = 0; b < WT; b++) asm volatile("" : "+a"(acc[a][b]));
+            if (g + 1 < nsteps) {
+                const bool same = st + 1 < nstage;
+                arrive(g + 1, same ? st + 1 : 0, same ? i : i + 1);
+                if (g + NB < nsteps) issue_next();
+                read_round((g + 1) % NB, 0, xa0, xb0);
             }
-            if (g + NB - 1 < nsteps) issue_next();
-            compute(buf);
+            compute_round(xa1, xb1);
         }
         {
             // bit 0 of each sum -> packed words.  A ballot over one accumulator
