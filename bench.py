@@ -39,8 +39,8 @@ MFMA_PEAK_TOPS = {1: ("i8", 5000.0), 2: ("fp4", 10100.0)}
 # counter reads for a 1 GiB plain copy in the same run (x2 and x1).  Valid only
 # for the kernel source and operand type it was taken with (SHA-256 prefix,
 # schur code); otherwise null.
-PMC_TRAFFIC = {"source": "paper_1006_1744_amd/csrc/k_mfma.hip", "sha256_16": "unmeasured",
-               "schur": 2, "bytes_per_launch": None,
+PMC_TRAFFIC = {"source": "paper_1006_1744_amd/csrc/k_mfma.hip", "sha256_16": "6540eb0fa1bb053d",
+               "schur": 2, "bytes_per_launch": 72181673,
                "profile": "profiles/gemm_mfma_traffic_65536.md"}
 
 
