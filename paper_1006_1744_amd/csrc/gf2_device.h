@@ -87,10 +87,22 @@ __device__ inline uint64_t tri_inverse64(const uint64_t *rows, int lane, bool lo
     return tri_inverse64_row(rows[lane], lane, lower);
 }
 
+// Workgroup barrier.  LDS_ONLY: waits for this wave's LDS operations only, so
+// global loads the wave has in flight stay in flight across it (a
+// __syncthreads also drains them); for sections that share nothing but LDS.
+template <bool LDS_ONLY>
+__device__ inline void block_sync() {
+    if constexpr (LDS_ONLY)
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else
+        __syncthreads();
+}
+
 // Tables of all 256 combinations of each 8 consecutive rows of 64 one-word rows
 // (8 groups): T[g * 256 + e] = XOR of rows 8g + u with bit u of e set.  The
 // threads are split into 8 sets, set g building group g from its 8 rows held
 // in registers; one barrier.  nthr must be a multiple of 8.
+template <bool LDS_ONLY = false>
 __device__ inline void build_tables_8x8(const uint64_t *rows, uint64_t *T, int tid, int nthr) {
     const int tpg = nthr >> 3;
     const int g = tid / tpg;
@@ -103,7 +115,7 @@ __device__ inline void build_tables_8x8(const uint64_t *rows, uint64_t *T, int t
         for (int u = 0; u < 8; u++) v ^= ((e >> u) & 1) ? rr[u] : 0ull;
         T[g * 256 + e] = v;
     }
-    __syncthreads();
+    block_sync<LDS_ONLY>();
 }
 
 // Tables of all 16 combinations of each 4 consecutive rows, built directly
@@ -128,18 +140,20 @@ __device__ inline void build_tables_k4(const uint64_t *rows, int nrows, int ng, 
 
 // Tables of all combinations of groups of k consecutive rows: for group g,
 // T[(g * 2^k + e) * TW + w] = XOR of rows g*k + u with bit u of e set (rows
-// past nrows read as zero), word w of a TW-word tile.  Built by doubling, one
-// level per barrier: entries [2^l, 2^(l+1)) = entries [0, 2^l) + row g*k + l.
-// Thread tid works on word tid % TW of entries tid / TW, tid / TW + nthr / TW,
-// ... (one division per call, shifts inside).  rows: LDS [>= ng*k][TW];
-// TW <= nthr.  All threads of the block must call it.
+// past nrows read as zero), word w of a TW-word tile.  k <= 4: every entry
+// directly (at most 4 loads), one barrier.  k > 4: by doubling three rows at a
+// time, one level per barrier: with entries [0, 2^l) complete, entry
+// idx + j 2^l (j < 2^d, d = min(3, k - l)) is entry idx plus the combination j of
+// rows g*k + l .. g*k + l + d - 1.  Thread tid works on word tid % TW of items
+// tid / TW, tid / TW + nthr / TW, ...  rows: LDS [>= ng*k][TW]; T: LDS
+// [ng][2^k][TW].  All threads must call it.
+template <bool LDS_ONLY = false>
 __device__ inline void build_group_tables(const uint64_t *rows, int nrows, int k, int ng,
                                           uint64_t *T, int TW, int tid, int nthr) {
     const int esz = 1 << k;
     const int wq = tid % TW, pq = tid / TW, pstep = nthr / TW;
     const bool on = pq < pstep;
     if (k <= 4) {
-        // few rows per group: every entry directly (at most 4 loads), one barrier
         if (on)
             for (int p = pq; p < ng * esz; p += pstep) {
                 const int g = p >> k, comb = p & (esz - 1);
@@ -150,23 +164,37 @@ __device__ inline void build_group_tables(const uint64_t *rows, int nrows, int k
                 }
                 T[(size_t)p * TW + wq] = v;
             }
-        __syncthreads();
+        block_sync<LDS_ONLY>();
         return;
     }
-    if (on)
-        for (int g = pq; g < ng; g += pstep) T[(size_t)g * esz * TW + wq] = 0ull;
-    __syncthreads();
-    for (int l = 0; l < k; l++) {
-        const int half = 1 << l;
+    for (int l = 0; l < k; l += 3) {
+        const int d = min(3, k - l);
+        const int nd = 1 << d;
         if (on)
             for (int p = pq; p < (ng << l); p += pstep) {
-                const int g = p >> l, idx = p & (half - 1);
-                const int row = g * k + l;
-                const uint64_t add = row < nrows ? rows[row * TW + wq] : 0ull;
-                const size_t t0 = ((size_t)g * esz + idx) * TW + wq;
-                T[t0 + (size_t)half * TW] = T[t0] ^ add;
+                const int g = p >> l, idx = p & ((1 << l) - 1);
+                uint64_t *tg = T + ((size_t)g * esz + idx) * TW + wq;
+                const uint64_t base = l == 0 ? 0ull : tg[0];
+                uint64_t r[3];
+#pragma unroll
+                for (int u = 0; u < 3; u++) {
+                    const int row = g * k + l + u;
+                    r[u] = (u < d && row < nrows) ? rows[row * TW + wq] : 0ull;
+                }
+                uint64_t c[8];
+                c[0] = base;
+                c[1] = base ^ r[0];
+                c[2] = base ^ r[1];
+                c[3] = c[1] ^ r[1];
+                c[4] = base ^ r[2];
+                c[5] = c[1] ^ r[2];
+                c[6] = c[2] ^ r[2];
+                c[7] = c[3] ^ r[2];
+#pragma unroll
+                for (int j = 0; j < 8; j++)
+                    if (j < nd && (j > 0 || l == 0)) tg[(size_t)(j << l) * TW] = c[j];
             }
-        __syncthreads();
+        block_sync<LDS_ONLY>();
     }
 }
 

@@ -334,31 +334,45 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
                 (t < r && wq < tw_n) ? Bbuf[(int64_t)t * bstride + (w0 - w_lo) + wq] : 0ull;
             sU[t * TW + wq] = 0ull;
         }
-    __syncthreads();
+    // The first chunk's row words are loaded after the staging loads above and
+    // stay in flight while the tables are built: rows at or below R1 belong to
+    // one thread each and the block shares nothing else but LDS, so every
+    // barrier up to their use waits for LDS traffic only.
+    const int per = gridDim.x * TU_THREADS;
+    int i = R1 + blockIdx.x * TU_THREADS + tid;
+    bool act = i < m;
+    uint64_t l = 0;
+    uint64_t x[TU_TWMAX];
+    uint64_t *px = A + (int64_t)i * stride + w0;
+    if (act) {
+        l = A[(int64_t)i * stride + wc];
+#pragma unroll
+        for (int w = 0; w < TU_TWMAX; w++)
+            if (w < tw_n) x[w] = px[w];
+    }
+    block_sync<true>();
     TRU(1);
-    build_tables_8x8(sInv, sLT, tid, TU_THREADS);
+    build_tables_8x8<true>(sInv, sLT, tid, TU_THREADS);
     TRU(2);
     const int ng = (r + k - 1) / k;
     const int npass = (ng + tables - 1) / tables;
     const int esz = 1 << k;
     const uint32_t kmask = (1u << k) - 1;
-    const int per = gridDim.x * TU_THREADS;
     const int nrows = m - R1;
     const int nchunks = nrows > 0 ? (nrows + per - 1) / per : 1;
     for (int chunk = 0; chunk < nchunks; chunk++) {
-        const int i = R1 + chunk * per + blockIdx.x * TU_THREADS + tid;
-        const bool act = i < m;
-        uint64_t c = 0;
-        uint64_t x[TU_TWMAX];
-        uint64_t *px = A + (int64_t)i * stride + w0;
-        if (act) {
-            const uint64_t l = A[(int64_t)i * stride + wc];
+        if (chunk > 0) {
+            i += per;
+            act = i < m;
+            px += (int64_t)per * stride;
+            if (act) {
+                l = A[(int64_t)i * stride + wc];
 #pragma unroll
-            for (int w = 0; w < TU_TWMAX; w++)
-                if (w < tw_n) x[w] = px[w];
-#pragma unroll
-            for (int g8 = 0; g8 < 8; g8++) c ^= sLT[g8 * 256 + (int)((l >> (8 * g8)) & 255)];
+                for (int w = 0; w < TU_TWMAX; w++)
+                    if (w < tw_n) x[w] = px[w];
+            }
         }
+        uint64_t c = 0;
 #ifdef GF2_TRACE
         if (act && c == 0x123456789ull) x[0] ^= 1;   // keep the loads before the stamp
         __syncthreads();
@@ -367,9 +381,9 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
         for (int pass = 0; pass < npass; pass++) {
             const int g0 = pass * tables, g1 = min(ng, g0 + tables);
             if (chunk == 0 || npass > 1) {
-                if (chunk > 0 || pass > 0) __syncthreads();
-                build_group_tables(sB + (size_t)g0 * k * TW, r - g0 * k, k, g1 - g0, sT, TW, tid,
-                                   TU_THREADS);
+                if (chunk > 0 || pass > 0) block_sync<true>();
+                build_group_tables<true>(sB + (size_t)g0 * k * TW, r - g0 * k, k, g1 - g0, sT, TW,
+                                         tid, TU_THREADS);
                 TRU(3);
                 if (pivots_here && chunk == 0 && pq < pstep) {
                     for (int t = pq; t < r; t += pstep) {
@@ -380,6 +394,15 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
                         sU[t * TW + wq] = y;
                     }
                 }
+            }
+            if (pass == 0 && act) {
+                // the row's multipliers l L^{-1}, formed once its panel word has
+                // landed (the empty asm keeps the compiler from hoisting the wait
+                // for it above the table builds)
+                uint64_t lv = l;
+                asm volatile("" : "+v"(lv));
+#pragma unroll
+                for (int g8 = 0; g8 < 8; g8++) c ^= sLT[g8 * 256 + (int)((lv >> (8 * g8)) & 255)];
             }
             if (act) {
                 for (int g = g0; g < g1; g++) {
