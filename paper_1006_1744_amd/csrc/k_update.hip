@@ -154,17 +154,16 @@ hipError_t launch_trsm_base(uint64_t *A, int64_t stride, const uint64_t *Lm, int
 // products would be too small to fill the device.
 constexpr int TB_THREADS = 1024;
 constexpr int TB_NB = 16;
-constexpr int TB_TW = 2;
 
-struct alignas(16) Word2 {
-    uint64_t a, b;
-};
-
+// TW words of X per block: 2 when there are enough word pairs to fill the
+// chip, else 1 (twice the blocks, half the LDS traffic per block and step;
+// every step is bound by the LDS reads of its table lookups).
+template <int TW>
 __global__ __launch_bounds__(TB_THREADS) void trsm_block_kernel(
     uint64_t *A, int64_t stride, const uint64_t *Lm, int64_t sl, int m, RowRange rows, int lw0,
     int w_lo, int w_hi, const int32_t *rk, int lower, int nbmax, const uint64_t *linv_store) {
-    __shared__ Word2 sX[TB_NB * 64];
-    __shared__ Word2 sT[256];
+    __shared__ __attribute__((aligned(16))) uint64_t sX[TB_NB * 64 * TW];
+    __shared__ __attribute__((aligned(16))) uint64_t sT[256 * TW];
     __shared__ uint64_t sInv[TB_NB * 64];
     __shared__ uint64_t sIT[TB_NB * 256];   // per diagonal block: 16 groups x 16 combinations of its inverse rows
     int r0, r1;
@@ -173,19 +172,22 @@ __global__ __launch_bounds__(TB_THREADS) void trsm_block_kernel(
     if (nr <= 1) return;
     const int nb = (nr + 63) / 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int w0 = w_lo + blockIdx.x * TB_TW;
-    const int tw_n = min(TB_TW, w_hi - w0);
+    const int w0 = w_lo + blockIdx.x * TW;
+    const int tw_n = min(TW, w_hi - w0);
     if (tw_n <= 0) return;
     const int row = tid, rb = row >> 6;
     const bool have = row < nr;
     // every load of this thread at once: its X words, its diagonal word and its
     // L words in solve order (step s uses block column lower ? s : nb - 1 - s)
-    Word2 x = {0ull, 0ull};
+    uint64_t x[TW];
+#pragma unroll
+    for (int w = 0; w < TW; w++) x[w] = 0ull;
     uint64_t dg = 0, lw[TB_NB];
     if (have) {
         const uint64_t *pa = A + (int64_t)(r0 + row) * stride + w0;
-        x.a = pa[0];
-        if (tw_n > 1) x.b = pa[1];
+#pragma unroll
+        for (int w = 0; w < TW; w++)
+            if (w < tw_n) x[w] = pa[w];
         const uint64_t *pl = Lm + (int64_t)(r0 + row) * sl + lw0;
         const int valid = nr - 64 * rb;
         dg = pl[rb] & (valid >= 64 ? ~0ull : ((1ull << valid) - 1));
@@ -199,7 +201,8 @@ __global__ __launch_bounds__(TB_THREADS) void trsm_block_kernel(
         const uint64_t cmask = cv >= 64 ? ~0ull : ((1ull << max(cv, 0)) - 1);
         lw[st] = (have && st < nb && later) ? Lm[(int64_t)(r0 + row) * sl + lw0 + c] & cmask : 0ull;
     }
-    sX[row] = x;
+#pragma unroll
+    for (int w = 0; w < TW; w++) sX[row * TW + w] = x[w];
     if (wave < nb) {
         const int P = lw0 + wave;   // the panel whose pivots these rows would be
         const bool stored = lower && linv_store && rk[P] == 64 * P && rk[P + 1] == 64 * P + 64 &&
@@ -232,27 +235,31 @@ __global__ __launch_bounds__(TB_THREADS) void trsm_block_kernel(
 #pragma unroll
             for (int g = 0; g < 16; g++) cp ^= sIT[b * 256 + (g << 4) + (int)((lv >> (4 * g)) & 15)];
         }
-        build_tables_k4<TB_TW>(&sX[64 * b].a, bn, 16, &sT[0].a, tid, TB_THREADS);
+        build_tables_k4<TW>(&sX[64 * b * TW], bn, 16, sT, tid, TB_THREADS);
         const uint64_t c = (rb == b && have) ? sInv[row] : cp;
         if (c) {
-            Word2 y = (rb == b) ? Word2{0ull, 0ull} : sX[row];
+            uint64_t y[TW];
+#pragma unroll
+            for (int w = 0; w < TW; w++) y[w] = (rb == b) ? 0ull : sX[row * TW + w];
 #pragma unroll
             for (int g = 0; g < 16; g++) {
-                const Word2 t = sT[(g << 4) + (int)((c >> (4 * g)) & 15)];
-                y.a ^= t.a;
-                y.b ^= t.b;
+                const uint64_t *t = &sT[((g << 4) + (int)((c >> (4 * g)) & 15)) * TW];
+#pragma unroll
+                for (int w = 0; w < TW; w++) y[w] ^= t[w];
             }
-            sX[row] = y;
+#pragma unroll
+            for (int w = 0; w < TW; w++) sX[row * TW + w] = y[w];
         } else if (rb == b && have) {
-            sX[row] = Word2{0ull, 0ull};
+#pragma unroll
+            for (int w = 0; w < TW; w++) sX[row * TW + w] = 0ull;
         }
         __syncthreads();
     }
     if (have) {
         uint64_t *pa = A + (int64_t)(r0 + row) * stride + w0;
-        const Word2 y = sX[row];
-        pa[0] = y.a;
-        if (tw_n > 1) pa[1] = y.b;
+#pragma unroll
+        for (int w = 0; w < TW; w++)
+            if (w < tw_n) pa[w] = sX[row * TW + w];
     }
 }
 
@@ -263,9 +270,14 @@ hipError_t launch_trsm_block(uint64_t *A, int64_t stride, const uint64_t *Lm, in
                              int lower, int nbmax, const uint64_t *linv_store, hipStream_t st) {
     if (w_hi <= w_lo) return hipSuccess;
     if (nbmax > TB_NB) nbmax = TB_NB;
-    int nb = (w_hi - w_lo + TB_TW - 1) / TB_TW;
-    hipLaunchKernelGGL(trsm_block_kernel, dim3(nb), dim3(TB_THREADS), 0, st, A, stride, Lm, sl, m,
-                       rows, lw0, w_lo, w_hi, rk, lower, nbmax, linv_store);
+    const int words = w_hi - w_lo;
+    if (words >= 512) {   // at least 256 blocks of word pairs
+        hipLaunchKernelGGL((trsm_block_kernel<2>), dim3((words + 1) / 2), dim3(TB_THREADS), 0, st, A,
+                           stride, Lm, sl, m, rows, lw0, w_lo, w_hi, rk, lower, nbmax, linv_store);
+    } else {
+        hipLaunchKernelGGL((trsm_block_kernel<1>), dim3(words), dim3(TB_THREADS), 0, st, A, stride, Lm,
+                           sl, m, rows, lw0, w_lo, w_hi, rk, lower, nbmax, linv_store);
+    }
     return hipGetLastError();
 }
 
