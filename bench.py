@@ -11,6 +11,9 @@ roofline: the dominant kernel (the MFMA Schur product): its algorithmic
 operations 2*M*N*K per launch over its mean launch time, timed with HIP events
 on the launch stream during the timed steps, against the dense matrix-core peak
 of the operand type the schedule uses (fp4 by default, int8 on request).
+int8_product: the same workload and schedule with the int8 matrix-core product
+instead of fp4 (step time, GF(2) ops/s, and its product roofline against the
+int8 dense peak); skipped with --no-int8 or an explicit --sched.
 cpu_baseline: the CPU oracle (Gaussian PLS, Appendix A) timed on a smaller
 matrix of the same kind on this host.
 batched: the batched workload (4096 matrices, m and n log-uniform in
@@ -138,6 +141,8 @@ def main() -> int:
     ap.add_argument("--no-rref", action="store_true")
     ap.add_argument("--sched", type=str, default="")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-int8", action="store_true",
+                    help="skip the second leg that times the same workload with the int8 product")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, one plain device copy of this many MiB (a known-size "
                          "dispatch that calibrates hardware traffic counters)")
@@ -161,55 +166,65 @@ def main() -> int:
     A = synth.random_half(m, n, args.seed)
     host = g.to_device(A, "cpu")
     del A
-    nsteps = args.steps + args.warmup
-    copies = [host.to("cuda") for _ in range(nsteps)]
-    del host
     ws = g.workspace(max(g.pls_workspace_bytes(m, n, s), g.rref_workspace_bytes(m, n)))
     P = torch.empty(m, dtype=torch.int32, device="cuda")
     Q = torch.empty(n, dtype=torch.int32, device="cuda")
     rank = torch.empty(1, dtype=torch.int32, device="cuda")
-    R = torch.empty_like(copies[0])
+    R = torch.empty_like(host, device="cuda")
 
-    def step(i):
-        g.pls(copies[i], m, n, s, ws=ws, P=P, Q=Q, rank=rank)
-        if not args.no_rref:
-            g.rref(copies[i], m, n, Q, rank, R=R, ws=ws)
+    def timed_leg(sch, steps, warmup):
+        """warmup + steps PLS (+ RREF) steps under schedule sch, each on its own
+        pristine device copy staged before the timed region; returns the step
+        time (ms), the rank, the product-launch profile and the launch log."""
+        nsteps = steps + warmup
+        copies = [host.to("cuda") for _ in range(nsteps)]
 
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    g.prof_enable()
-    g.prof_read()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.warmup, nsteps):
-        step(i)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    launches = g.prof_launches()
-    prof = g.prof_read()
-    g.prof_disable()
-    alg_bytes = sum((M * K + N * K + 2 * M * N) / 8 for _, M, N, K in launches)
-    r = int(rank.item())
-    ms = (t1 - t0) * 1e3 / args.steps
+        def step(i):
+            g.pls(copies[i], m, n, sch, ws=ws, P=P, Q=Q, rank=rank)
+            if not args.no_rref:
+                g.rref(copies[i], m, n, Q, rank, R=R, ws=ws)
+
+        for i in range(warmup):
+            step(i)
+        torch.cuda.synchronize()
+        g.prof_enable()
+        g.prof_read()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(warmup, nsteps):
+            step(i)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        launches = g.prof_launches()
+        prof = g.prof_read()
+        g.prof_disable()
+        del copies
+        torch.cuda.empty_cache()
+        return (t1 - t0) * 1e3 / steps, int(rank.item()), prof, launches
+
+    def product_roofline(sch, prof, launches, steps, ms):
+        achieved = prof["ops"] / (prof["ms"] * 1e-3) / 1e12 if prof["ms"] > 0 else 0.0
+        schur = (sch if sch is not None else g.default_sched()).schur
+        if schur not in MFMA_PEAK_TOPS:
+            sys.exit("bench.py: the roofline is defined for the MFMA Schur products (schur 1 or 2)")
+        op_type, peak = MFMA_PEAK_TOPS[schur]
+        alg_bytes = sum((M * K + N * K + 2 * M * N) / 8 for _, M, N, K in launches)
+        return op_type, {
+            "bound": "mfma",
+            "kernel": f"gemm_dma_kernel<4> + gemm_dma_kernel<2> ({op_type} MFMA Schur product, "
+                      "256x256 and 128x128 tiles)",
+            "achieved": round(achieved, 1), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+            "traffic": pmc_traffic(schur),
+            "alg_bytes_per_launch": round(alg_bytes / max(len(launches), 1)),
+            "launches_per_step": prof["launches"] // max(steps, 1),
+            "mean_launch_us": round(prof["ms"] * 1e3 / max(prof["launches"], 1), 2),
+            "kernel_share_of_step": round(prof["ms"] / steps / ms, 3)}
+
+    ms, r, prof, launches = timed_leg(s, args.steps, args.warmup)
     ops = classical_ops(m, n, r)
     value = ops / (ms * 1e-3)
-
-    achieved = prof["ops"] / (prof["ms"] * 1e-3) / 1e12 if prof["ms"] > 0 else 0.0
-    schur = (s if s is not None else g.default_sched()).schur
-    if schur not in MFMA_PEAK_TOPS:
-        sys.exit("bench.py: the roofline is defined for the MFMA Schur products (schur 1 or 2)")
-    op_type, peak = MFMA_PEAK_TOPS[schur]
-    roofline = {"bound": "mfma",
-                "kernel": f"gemm_dma_kernel<4> + gemm_dma_kernel<2> ({op_type} MFMA Schur product, "
-                          "256x256 and 128x128 tiles)",
-                "achieved": round(achieved, 1), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": pmc_traffic(schur),
-                "alg_bytes_per_launch": round(alg_bytes / max(len(launches), 1)),
-                "launches_per_step": prof["launches"] // max(args.steps, 1),
-                "mean_launch_us": round(prof["ms"] * 1e3 / max(prof["launches"], 1), 2),
-                "kernel_share_of_step": round(prof["ms"] / args.steps / ms, 3)}
+    op_type, roofline = product_roofline(s, prof, launches, args.steps, ms)
     out = {"metric": "PLS+RREF of a dense random 65536x65536 GF(2) matrix (GF(2) ops/s)",
            "value": value, "unit": "GF(2) ops/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
@@ -219,8 +234,15 @@ def main() -> int:
                       "m": m, "n": n, "rank": r,
                       "schedule": str(s) if s is not None else str(g.default_sched())},
            "roofline": roofline}
-    del copies
-    torch.cuda.empty_cache()
+    if not args.no_int8 and not args.sched:
+        # the same workload with the int8 matrix-core product, against the int8 peak
+        s0 = g.default_sched()
+        s8 = g.Sched(s0.k, s0.tables, s0.cutoff, g.SCHUR_MFMA)
+        ms8, r8, prof8, launches8 = timed_leg(s8, args.steps, args.warmup)
+        _, roof8 = product_roofline(s8, prof8, launches8, args.steps, ms8)
+        out["int8_product"] = {"schedule": str(s8), "ms_per_step": round(ms8, 3),
+                               "value": classical_ops(m, n, r8) / (ms8 * 1e-3), "unit": "GF(2) ops/s",
+                               "roofline": roof8}
     if not args.no_batch:
         out["batched"] = batched_leg(g, torch, max(3, args.steps))
     if not args.no_cpu:

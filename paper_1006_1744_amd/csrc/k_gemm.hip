@@ -5,7 +5,7 @@
 //   C[i][j] ^= parity( popcount( A_i[0:K] AND Bt_j[0:K] ) ).
 // Variant X (this file) evaluates it on the vector ALUs: every 32-bit word
 // step is one AND-XOR (v_bitop3_b32 on gfx950) per output element, parity at
-// the end.  Variant M (k_mfma.hip) uses int8 matrix cores.
+// the end.  Variant M (k_mfma.hip) uses the matrix cores (fp4 or int8).
 #include "gf2_internal.h"
 
 namespace gf2 {
@@ -36,10 +36,14 @@ __device__ inline uint64_t transpose64(uint64_t v, int lane) {
     return v;
 }
 
-__global__ __launch_bounds__(256) void transpose_kernel(const uint64_t *B, int64_t sb, int m,
-                                                        RowRange brows, int w_lo, int nw, int kmax,
-                                                        uint64_t *Bt, int64_t sbt,
-                                                        const int32_t *rk) {
+// Bt[64 jw + c][kw] <- bits c of words jw of B rows 64 kw .. 64 kw + 63 (rows at
+// or past K read as zero).
+// Small transposes: one wave per 64 x 64 block, each lane loading its row's word
+// and storing its column's word directly (the most blocks in flight).
+__global__ __launch_bounds__(256) void transpose_direct_kernel(const uint64_t *B, int64_t sb, int m,
+                                                               RowRange brows, int w_lo, int nw,
+                                                               int kmax, uint64_t *Bt, int64_t sbt,
+                                                               const int32_t *rk) {
     int b0, b1;
     eval_range(rk, m, brows, b0, b1);
     const int K = b1 - b0;
@@ -57,14 +61,60 @@ __global__ __launch_bounds__(256) void transpose_kernel(const uint64_t *B, int64
     }
 }
 
+// Large transposes: a block stages a tile of 64 rows x 16 words through
+// LDS (each row's 16 words are one 128-byte read), then each wave transposes
+// 64 x 64 blocks of it in registers.  Tiles are dealt so that the blocks of one
+// XCD walk consecutive kw of one word group: the output words a line of Bt
+// gathers from several tiles are then written through one L2.
+constexpr int TP_JW = 16;
+
+__global__ __launch_bounds__(256) void transpose_kernel(const uint64_t *B, int64_t sb, int m,
+                                                        RowRange brows, int w_lo, int nw, int kmax,
+                                                        uint64_t *Bt, int64_t sbt,
+                                                        const int32_t *rk) {
+    __shared__ uint64_t sT[64][TP_JW + 1];
+    int b0, b1;
+    eval_range(rk, m, brows, b0, b1);
+    const int K = b1 - b0;
+    const int nkw = (kmax + 63) / 64;
+    const int njb = (nw + TP_JW - 1) / TP_JW;
+    const int total = nkw * njb;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int per = gridDim.x / 8;
+    const int vid = (gridDim.x % 8 == 0) ? (blockIdx.x % 8) * per + blockIdx.x / 8 : blockIdx.x;
+    for (int t = vid; t < total; t += gridDim.x) {
+        const int kw = t % nkw, jb = t / nkw;
+        for (int e = threadIdx.x; e < 64 * TP_JW; e += 256) {
+            const int r = e / TP_JW, w = e % TP_JW;
+            const int row = 64 * kw + r, jw = jb * TP_JW + w;
+            sT[r][w] = (row < K && jw < nw) ? B[(int64_t)(b0 + row) * sb + w_lo + jw] : 0ull;
+        }
+        __syncthreads();
+        for (int j = wave; j < TP_JW; j += 4) {
+            const int jw = jb * TP_JW + j;
+            if (jw < nw) {
+                const uint64_t v = transpose64(sT[lane][j], lane);
+                Bt[(int64_t)(64 * jw + lane) * sbt + kw] = v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 hipError_t launch_transpose(const uint64_t *B, int64_t sb, int m, RowRange brows, int w_lo,
                             int nw, int kmax, uint64_t *Bt, int64_t sbt, const int32_t *rk,
                             hipStream_t st) {
-    int nkw = (kmax + 63) / 64;
-    int64_t total = (int64_t)nkw * nw;
-    if (total <= 0) return hipSuccess;
-    int64_t blocks = (total + 3) / 4;
-    if (blocks > 4096) blocks = 4096;
+    const int nkw = (kmax + 63) / 64;
+    if ((int64_t)nkw * nw <= 0) return hipSuccess;
+    if ((int64_t)nkw * nw < 16384) {
+        const int64_t blocks = ((int64_t)nkw * nw + 3) / 4;
+        hipLaunchKernelGGL(transpose_direct_kernel, dim3((unsigned)blocks), dim3(256), 0, st, B, sb,
+                           m, brows, w_lo, nw, kmax, Bt, sbt, rk);
+        return hipGetLastError();
+    }
+    const int64_t total = (int64_t)nkw * ((nw + TP_JW - 1) / TP_JW);
+    int64_t blocks = total < 2048 ? total : 2048;
+    if (blocks >= 8) blocks = blocks / 8 * 8;
     hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)blocks), dim3(256), 0, st, B, sb, m, brows,
                        w_lo, nw, kmax, Bt, sbt, rk);
     return hipGetLastError();
