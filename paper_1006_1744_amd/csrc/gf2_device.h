@@ -40,23 +40,57 @@ __device__ inline uint64_t shfl_xor64(uint64_t v, int mask) {
     return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
 }
 
+// x of lane (lane ^ S), without LDS: v_permlane32_swap / v_permlane16_swap for
+// S = 32, 16 (each swaps the halves of a register pair; called with the same
+// register twice, its two results hold the other half's values), DPP row
+// rotations for S = 8, 4 (row_ror:n gives lane i the value of lane i - n
+// within its row of 16; S = 4 rotates by 12 in 4-lane banks 0 and 2 and by 4 in
+// banks 1 and 3), DPP quad permutations for S = 2, 1.
+template <int S>
+__device__ inline uint32_t lane_xor32(uint32_t x, int lane) {
+    if constexpr (S == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        return (lane & 32) ? r[0] : r[1];
+    } else if constexpr (S == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        return (lane & 16) ? r[0] : r[1];
+    } else if constexpr (S == 8) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xF, 0xF, false);
+    } else if constexpr (S == 4) {
+        const int p = __builtin_amdgcn_update_dpp(0, (int)x, 0x12C, 0xF, 0x5, false);
+        return (uint32_t)__builtin_amdgcn_update_dpp(p, (int)x, 0x124, 0xF, 0xA, false);
+    } else if constexpr (S == 2) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);
+    } else {
+        static_assert(S == 1, "lane distance");
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);
+    }
+}
+
+// One butterfly stage of the transpose: lanes i and i ^ S trade the S-bit
+// blocks that belong to each other (mh: the upper block of every 2S bits).  Each
+// lane sends its value already shifted toward the partner's position and keeps
+// its own half with one bit-field select.
+template <int S>
+__device__ inline uint64_t transpose_stage(uint64_t v, uint64_t mh, int lane) {
+    const bool up = (lane & S) != 0;
+    const uint64_t o = up ? (v << S) : (v >> S);
+    const uint64_t q = ((uint64_t)lane_xor32<S>((uint32_t)(o >> 32), lane) << 32) |
+                       lane_xor32<S>((uint32_t)o, lane);
+    const uint64_t keep = up ? mh : ~mh;
+    return (v & keep) | (q & ~keep);
+}
+
 // 64 x 64 bit transpose across a wave: lane i holds row i on entry and column i
 // on exit.  Six butterfly stages, each exchanging the s-bit of the row and
 // column indices between lanes i and i ^ s.
 __device__ inline uint64_t transpose64(uint64_t v, int lane) {
-    const uint64_t hi_mask[6] = {0xFFFFFFFF00000000ull, 0xFFFF0000FFFF0000ull,
-                                 0xFF00FF00FF00FF00ull, 0xF0F0F0F0F0F0F0F0ull,
-                                 0xCCCCCCCCCCCCCCCCull, 0xAAAAAAAAAAAAAAAAull};
-#pragma unroll
-    for (int k = 0; k < 6; k++) {
-        const int s = 32 >> k;
-        const uint64_t mh = hi_mask[k];
-        uint64_t p = shfl_xor64(v, s);
-        if ((lane & s) == 0)
-            v = (v & ~mh) | ((p & ~mh) << s);
-        else
-            v = (v & mh) | ((p & mh) >> s);
-    }
+    v = transpose_stage<32>(v, 0xFFFFFFFF00000000ull, lane);
+    v = transpose_stage<16>(v, 0xFFFF0000FFFF0000ull, lane);
+    v = transpose_stage<8>(v, 0xFF00FF00FF00FF00ull, lane);
+    v = transpose_stage<4>(v, 0xF0F0F0F0F0F0F0F0ull, lane);
+    v = transpose_stage<2>(v, 0xCCCCCCCCCCCCCCCCull, lane);
+    v = transpose_stage<1>(v, 0xAAAAAAAAAAAAAAAAull, lane);
     return v;
 }
 

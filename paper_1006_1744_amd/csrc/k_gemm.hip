@@ -6,35 +6,10 @@
 // Variant X (this file) evaluates it on the vector ALUs: every 32-bit word
 // step is one AND-XOR (v_bitop3_b32 on gfx950) per output element, parity at
 // the end.  Variant M (k_mfma.hip) uses the matrix cores (fp4 or int8).
+#include "gf2_device.h"
 #include "gf2_internal.h"
 
 namespace gf2 {
-
-__device__ inline uint64_t shfl_xor64(uint64_t v, int mask) {
-    int lo = __shfl_xor((int)(uint32_t)v, mask);
-    int hi = __shfl_xor((int)(uint32_t)(v >> 32), mask);
-    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-}
-
-// 64 x 64 bit transpose across a wave: lane i holds row i on entry and column i
-// on exit.  Six butterfly stages, each exchanging the s-bit of the row and
-// column indices between lanes i and i ^ s.
-__device__ inline uint64_t transpose64(uint64_t v, int lane) {
-    const uint64_t hi_mask[6] = {0xFFFFFFFF00000000ull, 0xFFFF0000FFFF0000ull,
-                                 0xFF00FF00FF00FF00ull, 0xF0F0F0F0F0F0F0F0ull,
-                                 0xCCCCCCCCCCCCCCCCull, 0xAAAAAAAAAAAAAAAAull};
-#pragma unroll
-    for (int k = 0; k < 6; k++) {
-        const int s = 32 >> k;
-        const uint64_t mh = hi_mask[k];
-        uint64_t p = shfl_xor64(v, s);
-        if ((lane & s) == 0)
-            v = (v & ~mh) | ((p & ~mh) << s);
-        else
-            v = (v & mh) | ((p & mh) >> s);
-    }
-    return v;
-}
 
 // Bt[64 jw + c][kw] <- bits c of words jw of B rows 64 kw .. 64 kw + 63 (rows at
 // or past K read as zero).
