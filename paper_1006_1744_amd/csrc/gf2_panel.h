@@ -53,15 +53,20 @@ struct PanelInfo {
 // Build tables for pivots [ta, tb) (consecutive columns q[ta], q[ta]+1, ...):
 // group g holds pivots ta+8g .. ; entry [key] added to a row whose group bits
 // read `key` clears them to the multipliers and reduces the bits above.  The
-// threads are split into 8 sets, set g building group g: a thread reads its
-// group's 8 (masked) pivot rows from LDS once, then forms its entries from
-// registers.  nthr must be a multiple of 8.
+// NTHR threads are split into 8 sets of NTHR / 8 (a power of two), set g
+// building group g: a thread reads its group's 8 (masked) pivot rows from LDS
+// once; its combinations share their low log2(NTHR / 8) bits, whose part of
+// the sum it forms once, and it walks the high bits in Gray-code order, one
+// XOR per entry.  No barrier inside.
+template <int NTHR>
 __device__ inline void build_tables(const uint64_t *U, const int32_t *q, int ta, int tb,
-                                    uint64_t (*T)[256], int tid, int nthr) {
+                                    uint64_t (*T)[256], int tid) {
+    constexpr int TPG = NTHR / 8;
+    static_assert(TPG > 0 && (TPG & (TPG - 1)) == 0 && TPG <= 256, "threads per group");
+    constexpr int LB = __builtin_ctz(TPG);   // low bits fixed per thread
     const int np = tb - ta;
     const int ng = (np + 7) >> 3;
-    const int tpg = nthr >> 3;
-    const int g = tid / tpg;
+    const int g = tid / TPG;
     if (g >= ng) return;
     const int gs = min(8, np - 8 * g);
     uint64_t uu[8];
@@ -72,12 +77,20 @@ __device__ inline void build_tables(const uint64_t *U, const int32_t *q, int ta,
         uu[u] = U[s] & (~0ull << (q[s] & 63)) & keep;
     }
     const int off = q[ta] + 8 * g;
-    for (int comb = tid - g * tpg; comb < (1 << gs); comb += tpg) {
-        uint64_t v = 0;
+    const int base = tid - g * TPG;
+    uint64_t vlow = 0;
 #pragma unroll
-        for (int u = 0; u < 8; u++) v ^= ((comb >> u) & 1) ? uu[u] : 0ull;
-        const int key = (int)((v >> off) & ((1u << gs) - 1));
-        T[g][key] = v ^ ((uint64_t)comb << off);
+    for (int u = 0; u < LB; u++) vlow ^= ((base >> u) & 1) ? uu[u] : 0ull;
+    uint64_t vh = 0;
+#pragma unroll
+    for (int i = 0; i < (256 >> LB); i++) {
+        if (i > 0) vh ^= uu[LB + __builtin_ctz(i)];   // Gray codes i - 1 and i differ there
+        const int comb = base + ((i ^ (i >> 1)) << LB);
+        if (comb < (1 << gs)) {
+            const uint64_t v = vlow ^ vh;
+            const int key = (int)((v >> off) & ((1u << gs) - 1));
+            T[g][key] = v ^ ((uint64_t)comb << off);
+        }
     }
 }
 
@@ -182,7 +195,7 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
         if (mrem <= 0 || c >= nc || t >= mrem) break;
         if (epochs > 0) simple = false;
         const bool need_tab = F < mrem && t > pa && (tl != pa || th != t);
-        if (need_tab) build_tables(sU, sQ, pa, t, sT, tid, LEAF_THREADS);
+        if (need_tab) build_tables<LEAF_THREADS>(sU, sQ, pa, t, sT, tid);
         __syncthreads();
         if (need_tab && tid == 0) { s_tab_lo = pa; s_tab_hi = t; }
         const int ts = t;
@@ -315,7 +328,7 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
         // Rows between the window and an older frontier miss this epoch's pivots.
         const int wend = min(ts + LEAF_W, mrem);
         if (t1 > ts && F > wend) {
-            build_tables(sU, sQ, ts, t1, sE, tid, LEAF_THREADS);
+            build_tables<LEAF_THREADS>(sU, sQ, ts, t1, sE, tid);
             __syncthreads();
             for (int o = wend + tid; o < F; o += LEAF_THREADS)
                 col[(int64_t)o * stride] = apply_tables(col[(int64_t)o * stride], sQ, ts, t1, sE);
@@ -329,7 +342,7 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
         const int F2 = s_F, pa2 = s_pa, tl2 = s_tab_lo, th2 = s_tab_hi;
         __syncthreads();
         const bool need2 = F2 < mrem && t1 > pa2 && (tl2 != pa2 || th2 != t1);
-        if (need2) build_tables(sU, sQ, pa2, t1, sT, tid, LEAF_THREADS);
+        if (need2) build_tables<LEAF_THREADS>(sU, sQ, pa2, t1, sT, tid);
         if (tid == 0) s_far = NOHIT;
         __syncthreads();
         if (need2 && tid == 0) { s_tab_lo = pa2; s_tab_hi = t1; }

@@ -69,7 +69,7 @@ __device__ void batch_post(uint64_t *A, int64_t stride, int m, int nw, int b, in
             L.sQ[tid] = I.q[tid];
         }
         __syncthreads();
-        if (pend) build_tables(L.sU, L.sQ, pa, r, L.sT, tid, BT_THREADS);
+        if (pend) build_tables<BT_THREADS>(L.sU, L.sQ, pa, r, L.sT, tid);
         __syncthreads();
         uint64_t *col = A + (int64_t)R * stride + b;
         for (int o = tid; o < mrem; o += BT_THREADS) {

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
         }
         __syncthreads();
         TRP(1);
-        if (pend) build_tables(sU, sQ, pa, r, sT, tid, POST_THREADS);
+        if (pend) build_tables<POST_THREADS>(sU, sQ, pa, r, sT, tid);
         __syncthreads();
         TRP(2);
         uint64_t *col = Ab + (int64_t)R * sb + wc;   // the panel word lies in the block
