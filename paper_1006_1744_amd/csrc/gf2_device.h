@@ -134,20 +134,28 @@ __device__ inline void block_sync() {
 
 // Tables of all 256 combinations of each 8 consecutive rows of 64 one-word rows
 // (8 groups): T[g * 256 + e] = XOR of rows 8g + u with bit u of e set.  The
-// threads are split into 8 sets, set g building group g from its 8 rows held
-// in registers; one barrier.  nthr must be a multiple of 8.
-template <bool LDS_ONLY = false>
-__device__ inline void build_tables_8x8(const uint64_t *rows, uint64_t *T, int tid, int nthr) {
-    const int tpg = nthr >> 3;
-    const int g = tid / tpg;
+// NTHR threads are split into 8 sets of NTHR / 8 (a power of two), set g
+// building group g from its 8 rows held in registers; a thread's entries share
+// their low log2(NTHR / 8) bits, whose part of the XOR it forms once, and it
+// walks the high bits in Gray-code order, one XOR per entry.  One barrier.
+template <int NTHR, bool LDS_ONLY = false>
+__device__ inline void build_tables_8x8(const uint64_t *rows, uint64_t *T, int tid) {
+    constexpr int TPG = NTHR / 8;
+    static_assert(TPG > 0 && (TPG & (TPG - 1)) == 0 && TPG <= 256, "threads per group");
+    constexpr int LB = __builtin_ctz(TPG);
+    const int g = tid / TPG;
+    const int base = tid - g * TPG;
     uint64_t rr[8];
 #pragma unroll
     for (int u = 0; u < 8; u++) rr[u] = rows[8 * g + u];
-    for (int e = tid - g * tpg; e < 256; e += tpg) {
-        uint64_t v = 0;
+    uint64_t vlow = 0;
 #pragma unroll
-        for (int u = 0; u < 8; u++) v ^= ((e >> u) & 1) ? rr[u] : 0ull;
-        T[g * 256 + e] = v;
+    for (int u = 0; u < LB; u++) vlow ^= ((base >> u) & 1) ? rr[u] : 0ull;
+    uint64_t vh = 0;
+#pragma unroll
+    for (int i = 0; i < (256 >> LB); i++) {
+        if (i > 0) vh ^= rr[LB + __builtin_ctz(i)];   // Gray codes i - 1 and i differ there
+        T[g * 256 + base + ((i ^ (i >> 1)) << LB)] = vlow ^ vh;
     }
     block_sync<LDS_ONLY>();
 }

@@ -122,7 +122,7 @@ __device__ void batch_update(uint64_t *A, int64_t stride, int m, int nw, int b, 
     const int R1 = R + r;
     if (tid < 64) U.sInv[tid] = S.info.linv[tid];
     __syncthreads();
-    build_tables_8x8(U.sInv, U.sLT, tid, BT_THREADS);
+    build_tables_8x8<BT_THREADS>(U.sInv, U.sLT, tid);
     const int TW = batch_tile_words(k, tables);
     const int ng = (r + k - 1) / k, npass = (ng + tables - 1) / tables;
     const int esz = 1 << k;

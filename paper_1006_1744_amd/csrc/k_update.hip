@@ -364,7 +364,7 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
     }
     block_sync<true>();
     TRU(1);
-    build_tables_8x8<true>(sInv, sLT, tid, TU_THREADS);
+    build_tables_8x8<TU_THREADS, true>(sInv, sLT, tid);
     TRU(2);
     const int ng = (r + k - 1) / k;
     const int npass = (ng + tables - 1) / tables;
