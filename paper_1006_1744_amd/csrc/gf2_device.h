@@ -83,7 +83,8 @@ __device__ inline uint64_t transpose_stage(uint64_t v, uint64_t mh, int lane) {
 
 // 64 x 64 bit transpose across a wave: lane i holds row i on entry and column i
 // on exit.  Six butterfly stages, each exchanging the s-bit of the row and
-// column indices between lanes i and i ^ s.
+// column indices between lanes i and i ^ s.  Every lane of the wave must be
+// active (the exchanges read the partner lanes' registers).
 __device__ inline uint64_t transpose64(uint64_t v, int lane) {
     v = transpose_stage<32>(v, 0xFFFFFFFF00000000ull, lane);
     v = transpose_stage<16>(v, 0xFFFF0000FFFF0000ull, lane);
