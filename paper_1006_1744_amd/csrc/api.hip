@@ -85,17 +85,22 @@ hipEvent_t pool_event(gf2_ctx *ctx, size_t idx) {
     return ctx->pool[idx];
 }
 
+// pre_transposed: Bt already holds B transposed (kmax <= kMfmaMaxK, row stride
+// (kmax + 63) / 64 words, rows past K zero), so no transpose is launched.
 hipError_t enqueue_gemm(gf2_ctx *ctx, uint64_t *C, int64_t sc, const uint64_t *Am, int64_t sa,
                         const uint64_t *Bsrc, int64_t sb, int m, int kmrows, RowRange crows,
                         int aw, int cw, int nw, RowRange brows, int kmax, int schur,
-                        const int32_t *rk, uint64_t *Bt, hipStream_t st) {
+                        const int32_t *rk, uint64_t *Bt, hipStream_t st,
+                        bool pre_transposed = false) {
+    if (pre_transposed && kmax > kMfmaMaxK) return hipErrorInvalidValue;
     for (int k0 = 0; k0 < kmax; k0 += kMfmaMaxK) {
         const int kc = std::min(kMfmaMaxK, kmax - k0);
         RowRange br = brows;
         br.a += k0;
         br.s = std::min(br.s - k0, kc);
         const int64_t sbt = (kc + 63) / 64;
-        hipError_t e = launch_transpose(Bsrc, sb, kmrows, br, cw, nw, kc, Bt, sbt, rk, st);
+        hipError_t e = hipSuccess;
+        if (!pre_transposed) e = launch_transpose(Bsrc, sb, kmrows, br, cw, nw, kc, Bt, sbt, rk, st);
         if (e != hipSuccess) return e;
         int32_t *plog = nullptr;
         ProfRec rec{};
@@ -145,7 +150,9 @@ struct PlsDriver {
     gf2_sched s{};
     int32_t *rk = nullptr, *P = nullptr, *Q = nullptr, *info = nullptr;
     const uint64_t *linv = nullptr;   // L^{-1} rows inside the panel record
-    uint64_t *Bt = nullptr;
+    uint64_t *Bt = nullptr;           // a node's Schur operand, written transposed by its TRSM
+    uint64_t *Bt2 = nullptr;          // transposed operands of the products inside a TRSM
+    int64_t bt_sbt = 0;               // row stride of Bt for the node being solved
     uint64_t *Bbuf = nullptr;         // staged pivot rows, 64 x bstride words
     uint64_t *linv_store = nullptr;   // per panel: L^{-1} of its pivot block (64 words)
     uint64_t *pbuf = nullptr;         // base block copy: m rows x pbuf_w words, contiguous
@@ -153,6 +160,7 @@ struct PlsDriver {
     int64_t bstride = 0;
     int cus = 256;
     size_t bt_words = 0;   // capacity (launch) or requirement (dry)
+    size_t bt2_words = 0;
     hipStream_t st = nullptr;
     hipError_t err = hipSuccess;
 
@@ -161,26 +169,40 @@ struct PlsDriver {
     }
 
     // C rows `crows`, C words [cw, cw + nw) += A (rows = crows, K bits from word aw)
-    // times B (rows `brows`, same words as C), K <= kmax.
+    // times B (rows `brows`, same words as C), K <= kmax.  Inside a TRSM: B is
+    // transposed into Bt2 first.
     void gemm(RowRange crows, int aw, int cw, int nw, RowRange brows, int kmax) {
+        if (nw <= 0 || kmax <= 0) return;
+        if (dry) {
+            bt2_words = std::max(bt2_words, gemm_bt_words(nw, kmax));
+            return;
+        }
+        chk(enqueue_gemm(ctx, A, stride, A, stride, A, stride, m, m, crows, aw, cw, nw, brows,
+                         kmax, s.schur, rk, Bt2, st));
+    }
+
+    // A node's Schur product: B was written transposed into Bt by the TRSM that
+    // produced it (row stride bt_sbt = kmax / 64 words).
+    void gemm_schur(RowRange crows, int aw, int cw, int nw, RowRange brows, int kmax) {
         if (nw <= 0 || kmax <= 0) return;
         if (dry) {
             bt_words = std::max(bt_words, gemm_bt_words(nw, kmax));
             return;
         }
         chk(enqueue_gemm(ctx, A, stride, A, stride, A, stride, m, m, crows, aw, cw, nw, brows,
-                         kmax, s.schur, rk, Bt, st));
+                         kmax, s.schur, rk, Bt, st, true));
     }
 
     // rows [rk[ib] + a, min(rk[ie], rk[ib] + a + sz)) <- L^{-1} rows, L's block
-    // starting at word lw0 + a / 64; right-hand side words [w_lo, w_hi).
+    // starting at word lw0 + a / 64; right-hand side words [w_lo, w_hi).  The
+    // solved rows also go to Bt, transposed, at K word a / 64 (row stride bt_sbt).
     void trsm_lower(int ib, int ie, int a, int sz, int lw0, int w_lo, int w_hi) {
         if (w_hi <= w_lo || sz <= 0) return;
         if (sz <= trsm_block_max_rows()) {
             if (!dry)
                 chk(launch_trsm_block(A, stride, A, stride, m, row_range(ib, ie, a, sz),
                                       lw0 + a / 64, w_lo, w_hi, rk, 1, (sz + 63) / 64, linv_store,
-                                      st));
+                                      Bt, bt_sbt, a / 64, st));
             return;
         }
         const int h = (sz / 64 / 2) * 64;
@@ -228,11 +250,13 @@ struct PlsDriver {
         }
         const int h = nwd / 2;
         node(wb, h);
-        // A_NE <- L_NW^{-1} A_NE on the first half's pivot rows
+        // A_NE <- L_NW^{-1} A_NE on the first half's pivot rows, also written
+        // transposed into Bt for the Schur product
+        bt_sbt = h;
         trsm_lower(wb, wb + h, 0, 64 * h, wb, wb + h, wb + nwd);
         // A_SE <- A_SE + A_SW A_NE
-        gemm(row_range(wb + h, -1, 0, kINF), wb, wb + h, nwd - h, row_range(wb, wb + h, 0, 64 * h),
-             64 * h);
+        gemm_schur(row_range(wb + h, -1, 0, kINF), wb, wb + h, nwd - h,
+                   row_range(wb, wb + h, 0, 64 * h), 64 * h);
         node(wb + h, nwd - h);
         if (!dry)
             chk(launch_compress_shift(A, stride, m, 64 * wb, 64 * h, rk, wb, wb + h, wb + nwd, st));
@@ -245,9 +269,9 @@ struct PlsDriver {
 };
 
 struct PlsLayout {
-    size_t rk_off, info_off, bt_off, bb_off, linv_off, pbuf_off, total;
+    size_t rk_off, info_off, bt_off, bt2_off, bb_off, linv_off, pbuf_off, total;
     int pbuf_w;
-    size_t bt_words;
+    size_t bt_words, bt2_words;
     int64_t bstride;
 };
 
@@ -268,6 +292,9 @@ PlsLayout pls_layout(int64_t m, int64_t n, const gf2_sched &s) {
     L.bt_off = off;
     L.bt_words = d.bt_words;
     off = align_up(off + d.bt_words * 8);
+    L.bt2_off = off;
+    L.bt2_words = d.bt2_words;
+    off = align_up(off + d.bt2_words * 8);
     L.bb_off = off;
     L.bstride = std::max<int64_t>(d.bstride, 1);
     off = align_up(off + (size_t)64 * L.bstride * 8);
@@ -431,6 +458,8 @@ int gf2_pls(gf2_ctx *ctx, gf2_mat A, int32_t *P, int32_t *Q, int32_t *rank, cons
     d.info = (int32_t *)(base + L.info_off);
     d.Bt = (uint64_t *)(base + L.bt_off);
     d.bt_words = L.bt_words;
+    d.Bt2 = (uint64_t *)(base + L.bt2_off);
+    d.bt2_words = L.bt2_words;
     d.Bbuf = (uint64_t *)(base + L.bb_off);
     d.bstride = L.bstride;
     d.linv = (const uint64_t *)(base + L.info_off + panel_info_linv_offset());
@@ -536,7 +565,7 @@ struct UpperSolve {
         if (a >= r || sz <= 0) return;
         if (sz <= trsm_block_max_rows()) {
             chk(launch_trsm_block(X, sx, U, su, r, row_range(-1, -1, a, sz), a / 64, 0, nwx, rr, 0,
-                                  (sz + 63) / 64, nullptr, st));
+                                  (sz + 63) / 64, nullptr, nullptr, 0, 0, st));
             return;
         }
         const int h = (sz / 64 / 2) * 64;

@@ -79,9 +79,14 @@ hipError_t launch_trsm_base(uint64_t *A, int64_t stride, const uint64_t *Lm, int
 // X <- T^{-1} X for up to nbmax (<= trsm_block_max_rows() / 64) blocks of 64 rows
 // `rows` of A; T's rows are the same rows of Lm, the block of 64 columns starting
 // at word lw0 (diagonal block b at word lw0 + b).  lower = 0: unit upper.
+// Bt (nullable): the solved rows are also written transposed for a following
+// product whose K rows start nbmax-block-aligned at this call's first row: word
+// kw0 + v of Bt rows 64 (w - w_lo) + c (row stride sbt words) receives bit c of
+// word w of rows 64 v .. 64 v + 63, for v < nbmax (rows past the range as zero).
 hipError_t launch_trsm_block(uint64_t *A, int64_t stride, const uint64_t *Lm, int64_t sl, int m,
                              RowRange rows, int lw0, int w_lo, int w_hi, const int32_t *rk,
-                             int lower, int nbmax, const uint64_t *linv_store, hipStream_t st);
+                             int lower, int nbmax, const uint64_t *linv_store, uint64_t *Bt,
+                             int64_t sbt, int kw0, hipStream_t st);
 int trsm_block_max_rows();
 
 // Table-driven update after a panel (Section 4.1: MakeTable1 / AddRowsFromTable)

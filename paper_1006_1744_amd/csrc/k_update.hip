@@ -161,7 +161,8 @@ constexpr int TB_NB = 16;
 template <int TW>
 __global__ __launch_bounds__(TB_THREADS) void trsm_block_kernel(
     uint64_t *A, int64_t stride, const uint64_t *Lm, int64_t sl, int m, RowRange rows, int lw0,
-    int w_lo, int w_hi, const int32_t *rk, int lower, int nbmax, const uint64_t *linv_store) {
+    int w_lo, int w_hi, const int32_t *rk, int lower, int nbmax, const uint64_t *linv_store,
+    uint64_t *Bt, int64_t sbt, int kw0) {
     __shared__ __attribute__((aligned(16))) uint64_t sX[TB_NB * 64 * TW];
     __shared__ __attribute__((aligned(16))) uint64_t sT[256 * TW];
     __shared__ uint64_t sInv[TB_NB * 64];
@@ -169,8 +170,9 @@ __global__ __launch_bounds__(TB_THREADS) void trsm_block_kernel(
     int r0, r1;
     eval_range(rk, m, rows, r0, r1);
     const int nr = min(r1 - r0, nbmax * 64);
-    if (nr <= 1) return;
-    const int nb = (nr + 63) / 64;
+    // at most one row: nothing to solve, but a transposed copy is still owed
+    if (nr <= 1 && Bt == nullptr) return;
+    const int nb = max(nr + 63, 0) / 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int w0 = w_lo + blockIdx.x * TW;
     const int tw_n = min(TW, w_hi - w0);
@@ -261,22 +263,35 @@ __global__ __launch_bounds__(TB_THREADS) void trsm_block_kernel(
         for (int w = 0; w < TW; w++)
             if (w < tw_n) pa[w] = sX[row * TW + w];
     }
+    if (Bt != nullptr && wave < nbmax) {
+        // the solved rows as the next product's transposed operand: wave v holds
+        // rows 64 v .. 64 v + 63 (zero past nr), one 64 x 64 block per word, which
+        // becomes word kw0 + v of Bt rows 64 (w - w_lo) .. 64 (w - w_lo) + 63
+#pragma unroll
+        for (int w = 0; w < TW; w++)
+            if (w < tw_n) {
+                const uint64_t t = transpose64(sX[row * TW + w], lane);
+                Bt[(int64_t)(64 * (w0 - w_lo + w) + lane) * sbt + kw0 + wave] = t;
+            }
+    }
 }
 
 int trsm_block_max_rows() { return TB_NB * 64; }
 
 hipError_t launch_trsm_block(uint64_t *A, int64_t stride, const uint64_t *Lm, int64_t sl, int m,
                              RowRange rows, int lw0, int w_lo, int w_hi, const int32_t *rk,
-                             int lower, int nbmax, const uint64_t *linv_store, hipStream_t st) {
+                             int lower, int nbmax, const uint64_t *linv_store, uint64_t *Bt,
+                             int64_t sbt, int kw0, hipStream_t st) {
     if (w_hi <= w_lo) return hipSuccess;
     if (nbmax > TB_NB) nbmax = TB_NB;
     const int words = w_hi - w_lo;
     if (words >= 512) {   // at least 256 blocks of word pairs
         hipLaunchKernelGGL((trsm_block_kernel<2>), dim3((words + 1) / 2), dim3(TB_THREADS), 0, st, A,
-                           stride, Lm, sl, m, rows, lw0, w_lo, w_hi, rk, lower, nbmax, linv_store);
+                           stride, Lm, sl, m, rows, lw0, w_lo, w_hi, rk, lower, nbmax, linv_store,
+                           Bt, sbt, kw0);
     } else {
         hipLaunchKernelGGL((trsm_block_kernel<1>), dim3(words), dim3(TB_THREADS), 0, st, A, stride, Lm,
-                           sl, m, rows, lw0, w_lo, w_hi, rk, lower, nbmax, linv_store);
+                           sl, m, rows, lw0, w_lo, w_hi, rk, lower, nbmax, linv_store, Bt, sbt, kw0);
     }
     return hipGetLastError();
 }

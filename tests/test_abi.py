@@ -53,9 +53,11 @@ def test_workspace_sizes(lib):
     assert lib.gf2_pls_workspace_bytes(-1, 10, None) == 0
     assert lib.gf2_pls_workspace_bytes(4096, 4096, None) > 0
     a = lib.gf2_pls_workspace_bytes(65536, 65536, None)
-    # the transposed product operand dominates: at most a quarter of the matrix,
-    # plus the base-block copy (at most 16 words per row) and small per-panel state
-    assert 0 < a <= 65536 * 65536 // 8 // 4 + 65536 * 16 * 8 + (1 << 20)
+    # the transposed product operands dominate: at most a quarter of the matrix for
+    # a node's Schur operand and an eighth for the products inside triangular
+    # solves, plus the base-block copy (at most 16 words per row) and small
+    # per-panel state
+    assert 0 < a <= 65536 * 65536 // 8 // 4 + 65536 * 65536 // 8 // 8 + 65536 * 16 * 8 + (1 << 20)
     assert lib.gf2_rref_workspace_bytes(100, 200) > 0
     assert lib.gf2_addmul_workspace_bytes(10, 10, 10) > 0
 
