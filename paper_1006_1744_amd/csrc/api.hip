@@ -153,6 +153,7 @@ struct PlsDriver {
     uint64_t *Bt = nullptr;           // a node's Schur operand, written transposed by its TRSM
     uint64_t *Bt2 = nullptr;          // transposed operands of the products inside a TRSM
     int64_t bt_sbt = 0;               // row stride of Bt for the node being solved
+    bool bt_fused = false;            // the node's TRSM writes Bt (else the product transposes)
     uint64_t *Bbuf = nullptr;         // staged pivot rows, 64 x bstride words
     uint64_t *linv_store = nullptr;   // per panel: L^{-1} of its pivot block (64 words)
     uint64_t *pbuf = nullptr;         // base block copy: m rows x pbuf_w words, contiguous
@@ -181,8 +182,8 @@ struct PlsDriver {
                          kmax, s.schur, rk, Bt2, st));
     }
 
-    // A node's Schur product: B was written transposed into Bt by the TRSM that
-    // produced it (row stride bt_sbt = kmax / 64 words).
+    // A node's Schur product: when bt_fused, B was written transposed into Bt by
+    // the TRSM that produced it (row stride bt_sbt = kmax / 64 words).
     void gemm_schur(RowRange crows, int aw, int cw, int nw, RowRange brows, int kmax) {
         if (nw <= 0 || kmax <= 0) return;
         if (dry) {
@@ -190,7 +191,7 @@ struct PlsDriver {
             return;
         }
         chk(enqueue_gemm(ctx, A, stride, A, stride, A, stride, m, m, crows, aw, cw, nw, brows,
-                         kmax, s.schur, rk, Bt, st, true));
+                         kmax, s.schur, rk, Bt, st, bt_fused));
     }
 
     // rows [rk[ib] + a, min(rk[ie], rk[ib] + a + sz)) <- L^{-1} rows, L's block
@@ -202,7 +203,7 @@ struct PlsDriver {
             if (!dry)
                 chk(launch_trsm_block(A, stride, A, stride, m, row_range(ib, ie, a, sz),
                                       lw0 + a / 64, w_lo, w_hi, rk, 1, (sz + 63) / 64, linv_store,
-                                      Bt, bt_sbt, a / 64, st));
+                                      bt_fused ? Bt : nullptr, bt_sbt, a / 64, st));
             return;
         }
         const int h = (sz / 64 / 2) * 64;
@@ -251,8 +252,11 @@ struct PlsDriver {
         const int h = nwd / 2;
         node(wb, h);
         // A_NE <- L_NW^{-1} A_NE on the first half's pivot rows, also written
-        // transposed into Bt for the Schur product
+        // transposed into Bt for the Schur product when the solve runs one word
+        // per block (below 512 words); wider ones leave it to the tiled transpose,
+        // cheaper than the scattered writes at the end of every solve block there
         bt_sbt = h;
+        bt_fused = nwd - h < 512;
         trsm_lower(wb, wb + h, 0, 64 * h, wb, wb + h, wb + nwd);
         // A_SE <- A_SE + A_SW A_NE
         gemm_schur(row_range(wb + h, -1, 0, kINF), wb, wb + h, nwd - h,
