@@ -43,7 +43,7 @@ MFMA_PEAK_TOPS = {1: ("i8", 5000.0), 2: ("fp4", 10100.0)}
 # for the kernel source and operand type it was taken with (SHA-256 prefix,
 # schur code); otherwise null.
 PMC_TRAFFIC = {"source": "paper_1006_1744_amd/csrc/k_mfma.hip", "sha256_16": "6540eb0fa1bb053d",
-               "schur": 2, "bytes_per_launch": 72176460,
+               "schur": 2, "bytes_per_launch": 72191526,
                "profile": "profiles/gemm_mfma_traffic_65536.md"}
 
 
