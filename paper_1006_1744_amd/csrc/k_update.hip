@@ -307,10 +307,11 @@ hipError_t launch_trsm_block(uint64_t *A, int64_t stride, const uint64_t *Lm, in
 // per table) and every row adds one table row per table (AddRowsFromTable);
 // l L^{-1} comes from tables of 8 rows of L^{-1}.  B is read only from the
 // staging buffer, so blocks never race on the pivot rows they rewrite.
-// One thread owns one row and all TW (<= TU_TWMAX) words of the block's tile,
-// so l L^{-1} is formed once per row and the row's loads are issued together;
-// the grid is sized to be resident in one round.
-constexpr int TU_THREADS = 1024;   // one row per thread; 16 waves hide the table build's latency
+// A row is owned by 1, 2 or 4 threads, each with its share of the TW
+// (<= TU_TWMAX) words of the block's tile (each forms l L^{-1} itself), so the
+// rows spread over up to one block per CU; the grid is sized to be resident in
+// one round.
+constexpr int TU_THREADS = 1024;   // 16 waves hide the table build's latency
 constexpr int TU_TWMAX = 8;
 constexpr int TU_TABLE_LDS = 120 * 1024;   // budget for the B tables of one pass
 constexpr int TU_LDS_MAX = 150 * 1024;
@@ -329,7 +330,8 @@ size_t table_update_lds_bytes(int k, int tables, int TW) {
 
 __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
     uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk, int b, int w_lo, int w_hi,
-    int k, int tables, int TW, const uint64_t *linv, const uint64_t *Bbuf, int64_t bstride) {
+    int k, int tables, int TW, int lg_tpr, const uint64_t *linv, const uint64_t *Bbuf,
+    int64_t bstride) {
 #ifdef GF2_TRACE
     uint64_t *trace_upd = reinterpret_cast<uint64_t *>(const_cast<char *>(reinterpret_cast<const char *>(linv)) + 64 * 8 + 4 * 257 + 4 + 24 * 8 + 8 * 8);
 #define TRU(i) do { if (threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0 && b == 0) trace_upd[i] = __builtin_amdgcn_s_memrealtime(); } while (0)
@@ -361,21 +363,28 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
                 (t < r && wq < tw_n) ? Bbuf[(int64_t)t * bstride + (w0 - w_lo) + wq] : 0ull;
             sU[t * TW + wq] = 0ull;
         }
-    // The first chunk's row words are loaded after the staging loads above and
-    // stay in flight while the tables are built: rows at or below R1 belong to
-    // one thread each and the block shares nothing else but LDS, so every
-    // barrier up to their use waits for LDS traffic only.
-    const int per = gridDim.x * TU_THREADS;
-    int i = R1 + blockIdx.x * TU_THREADS + tid;
+    // 2^lg_tpr threads share a row: part p owns its words [p wpt, p wpt + wpt)
+    // of the tile (each forms the row's multipliers itself).  The first chunk's
+    // row words are loaded after the staging loads above and stay in flight
+    // while the tables are built: rows at or below R1 belong to their own
+    // threads and the block shares nothing else but LDS, so every barrier up to
+    // their use waits for LDS traffic only.
+    const int rpb = TU_THREADS >> lg_tpr;                 // rows per block
+    const int part = tid & ((1 << lg_tpr) - 1);
+    const int wpt = (TW + (1 << lg_tpr) - 1) >> lg_tpr;   // words per thread (<= TU_TWMAX)
+    const int wb = part * wpt;
+    const int wn = max(0, min(wpt, tw_n - wb));           // this thread's words
+    const int per = gridDim.x * rpb;
+    int i = R1 + blockIdx.x * rpb + (tid >> lg_tpr);
     bool act = i < m;
     uint64_t l = 0;
     uint64_t x[TU_TWMAX];
-    uint64_t *px = A + (int64_t)i * stride + w0;
+    uint64_t *px = A + (int64_t)i * stride + w0 + wb;
     if (act) {
         l = A[(int64_t)i * stride + wc];
 #pragma unroll
         for (int w = 0; w < TU_TWMAX; w++)
-            if (w < tw_n) x[w] = px[w];
+            if (w < wn) x[w] = px[w];
     }
     block_sync<true>();
     TRU(1);
@@ -396,7 +405,7 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
                 l = A[(int64_t)i * stride + wc];
 #pragma unroll
                 for (int w = 0; w < TU_TWMAX; w++)
-                    if (w < tw_n) x[w] = px[w];
+                    if (w < wn) x[w] = px[w];
             }
         }
         uint64_t c = 0;
@@ -433,17 +442,18 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
             }
             if (act) {
                 for (int g = g0; g < g1; g++) {
-                    const uint64_t *T = sT + ((size_t)(g - g0) * esz + ((c >> (k * g)) & kmask)) * TW;
+                    const uint64_t *T =
+                        sT + ((size_t)(g - g0) * esz + ((c >> (k * g)) & kmask)) * TW + wb;
 #pragma unroll
                     for (int w = 0; w < TU_TWMAX; w++)
-                        if (w < tw_n) x[w] ^= T[w];
+                        if (w < wn) x[w] ^= T[w];
                 }
             }
         }
         if (act) {
 #pragma unroll
             for (int w = 0; w < TU_TWMAX; w++)
-                if (w < tw_n) px[w] = x[w];
+                if (w < wn) px[w] = x[w];
         }
     }
     TRU(4);
@@ -462,7 +472,11 @@ hipError_t launch_table_update(uint64_t *A, int64_t stride, int m, int wc, const
     const int ny = (w_hi - w_lo + TW - 1) / TW;
     const size_t lds = table_update_lds_bytes(k, tables, TW);
     const int occ = std::max(1, (int)(CU_LDS / lds));
-    int nx = (m + TU_THREADS - 1) / TU_THREADS;
+    // threads per row: 4 from four words up, 2 for two or three, else 1, so that
+    // the rows spread over more blocks (each block builds the same tables)
+    const int lg_tpr = TW >= 4 ? 2 : (TW >= 2 ? 1 : 0);
+    const int rpb = TU_THREADS >> lg_tpr;
+    int nx = (m + rpb - 1) / rpb;
     const int fit = std::max(1, target_blocks * occ / ny);
     if (nx > fit) nx = fit;
     if (nx < 1) nx = 1;
@@ -474,7 +488,7 @@ hipError_t launch_table_update(uint64_t *A, int64_t stride, int m, int wc, const
         attr_set = true;
     }
     hipLaunchKernelGGL(table_update_kernel, dim3(nx, ny), dim3(TU_THREADS), lds, st, A, stride, m,
-                       wc, rk, b, w_lo, w_hi, k, tables, TW, linv, Bbuf, bstride);
+                       wc, rk, b, w_lo, w_hi, k, tables, TW, lg_tpr, linv, Bbuf, bstride);
     return hipGetLastError();
 }
 
