@@ -1,0 +1,102 @@
+"""Host-side checks of two encodings the GPU kernels rely on (pure Python models
+of the arithmetic, no GPU):
+
+* the matrix-core operand encodings of the Schur product: a lane's 32 K-bits
+  become fp4 (e2m1) nibbles or int8 bytes whose products, summed over every
+  (register, element), count exactly the K positions where both operands have a
+  one, so the parity of the sum is the GF(2) dot product;
+* the butterfly stage of the 64 x 64 bit transpose, in the form where each lane
+  sends its value already shifted toward the partner and keeps its own half with
+  one bit select: six stages give the transpose.
+"""
+import random
+
+import pytest
+
+# e2m1 (OCP MX fp4): sign, 2 exponent bits (bias 1), 1 mantissa bit; exponent 0
+# is subnormal (0.m * 2^0).
+def e2m1(code: int) -> float:
+    sign = -1.0 if code & 8 else 1.0
+    e, mnt = (code >> 1) & 3, code & 1
+    if e == 0:
+        return sign * 0.5 * mnt
+    return sign * (1.0 + 0.5 * mnt) * 2.0 ** (e - 1)
+
+
+def fp4_a(w: int) -> list[int]:
+    return [w & 0x11111111, w & 0x22222222, w & 0x44444444, (w >> 1) & 0x44444444]
+
+
+def fp4_b(w: int) -> list[int]:
+    return [(w << 2) & 0x44444444, w & 0x22222222, (w >> 2) & 0x11111111, (w >> 3) & 0x11111111]
+
+
+def i8_regs(w: int) -> list[int]:
+    return [(w >> (4 * s + v)) & 0x01010101 for s in (0, 1) for v in range(4)]
+
+
+def test_e2m1_table():
+    # the codes the encoding uses, and the full non-negative range
+    assert [e2m1(c) for c in range(8)] == [0.0, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0]
+    assert e2m1(0b1000) == 0.0 and e2m1(0b1010) == -1.0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_fp4_operands_count_matching_bits(seed):
+    rng = random.Random(seed)
+    words = [0, 0xFFFFFFFF, 1, 1 << 31, 0x80000001] + [rng.getrandbits(32) for _ in range(300)]
+    for wa in words:
+        for wb in rng.sample(words, 20):
+            ra, rb = fp4_a(wa), fp4_b(wb)
+            total = 0.0
+            for v in range(4):
+                for n in range(8):
+                    total += e2m1((ra[v] >> (4 * n)) & 15) * e2m1((rb[v] >> (4 * n)) & 15)
+            assert total == bin(wa & wb).count("1")
+
+
+def test_fp4_operands_map_each_bit_once():
+    # bit k of w lands in exactly one (register, nibble) on each side, the same one
+    for k in range(32):
+        pa = [(v, n) for v, r in enumerate(fp4_a(1 << k)) for n in range(8) if (r >> (4 * n)) & 15]
+        pb = [(v, n) for v, r in enumerate(fp4_b(1 << k)) for n in range(8) if (r >> (4 * n)) & 15]
+        assert len(pa) == 1 and pa == pb
+        v, n = pa[0]
+        assert e2m1((fp4_a(1 << k)[v] >> (4 * n)) & 15) * e2m1((fp4_b(1 << k)[v] >> (4 * n)) & 15) == 1.0
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_int8_operands_count_matching_bits(seed):
+    rng = random.Random(100 + seed)
+    for _ in range(500):
+        wa, wb = rng.getrandbits(32), rng.getrandbits(32)
+        ra, rb = i8_regs(wa), i8_regs(wb)
+        total = sum(((ra[j] >> (8 * t)) & 255) * ((rb[j] >> (8 * t)) & 255)
+                    for j in range(8) for t in range(4))
+        assert total == bin(wa & wb).count("1")
+
+
+M64 = (1 << 64) - 1
+HI = [0xFFFFFFFF00000000, 0xFFFF0000FFFF0000, 0xFF00FF00FF00FF00,
+      0xF0F0F0F0F0F0F0F0, 0xCCCCCCCCCCCCCCCC, 0xAAAAAAAAAAAAAAAA]
+
+
+def transpose_stages(rows: list[int]) -> list[int]:
+    v = list(rows)
+    for k in range(6):
+        s, mh = 32 >> k, HI[k]
+        sent = [((x << s) & M64) if (lane & s) else (x >> s) for lane, x in enumerate(v)]
+        q = [sent[lane ^ s] for lane in range(64)]
+        keep = [mh if (lane & s) else (~mh & M64) for lane in range(64)]
+        v = [(v[lane] & keep[lane]) | (q[lane] & ~keep[lane] & M64) for lane in range(64)]
+    return v
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_transpose_stages(seed):
+    rng = random.Random(seed)
+    rows = [rng.getrandbits(64) for _ in range(64)]
+    got = transpose_stages(rows)
+    want = [sum(((rows[i] >> j) & 1) << i for i in range(64)) for j in range(64)]
+    assert got == want
+    assert transpose_stages(got) == rows
