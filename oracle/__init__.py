@@ -16,12 +16,16 @@ Contents
 * checkers: unpacking L and S from the in-place result, applying P,
   reconstruction A = P L S, echelon-form checks, Freivalds' randomized product
   check (Freivalds 1977).
+* ``solve_from_pls`` / ``kernel_basis``: A x = b and a basis of the null space
+  from the PLS (forward substitution with L, back substitution with S).
 * ``pyref``: pure-Python statements of the paper's algorithms for tiny inputs.
 
 Parity status: every function here is pinned by tests in
 ``tests/test_oracle_pins.py`` (brute force on tiny inputs, the Figure 1 table,
 the Section 4.1 "[1 0 1]" example, reconstruction, rank(A) = rank(A^T),
-planted ranks, agreement of independent statements of the algorithm).
+planted ranks, agreement of independent statements of the algorithm); the
+solving functions by ``tests/test_oracle_solve.py`` (brute force over every x
+on tiny systems, consistency, null-space dimension and independence).
 """
 from __future__ import annotations
 
@@ -268,3 +272,53 @@ def freivalds(A: np.ndarray, m: int, n: int, r: int, P, Q, Ap, trials: int = 64,
         if not np.array_equal(lhs, rhs):
             return False
     return True
+
+
+# ---------------------------------------------------------------- solving
+# The decomposition as the building block for solving linear systems over GF(2)
+# (the abstract and Section 1): with P A = L S, a system A x = b becomes
+# L S x = P b, one forward substitution with L's unit lower triangle, a
+# consistency test on L's remaining rows, and one back substitution with the
+# echelon rows of S.  Written out on 0/1 arrays, for test sizes.
+
+def solve_from_pls(b: np.ndarray, m: int, n: int, r: int, P, Q, Ap):
+    """A solution x (0/1, length n, non-pivot entries 0) of A x = b, from A's PLS
+    (r, P, Q, A' as returned by ``pls``); None if the system is inconsistent.
+    b: 0/1 vector of length m."""
+    L, S = unpack_LS(Ap, m, n, r, Q)
+    c = apply_P(np.asarray(b, dtype=np.uint8).reshape(m, 1), P).reshape(m)
+    # L y = c on the first r rows (unit lower triangle)
+    y = np.zeros(r, dtype=np.uint8)
+    for i in range(r):
+        y[i] = c[i] ^ (int(L[i, :i].astype(np.int64) @ y[:i].astype(np.int64)) & 1)
+    # the remaining rows of L y must reproduce the remaining entries of c
+    if r < m:
+        rest = (L[r:].astype(np.int64) @ y.astype(np.int64)) & 1
+        if not np.array_equal(rest.astype(np.uint8), c[r:]):
+            return None
+    # S x = y: pivot columns Q[0] < Q[1] < ... from the last row up, others 0
+    x = np.zeros(n, dtype=np.uint8)
+    for i in range(r - 1, -1, -1):
+        q = int(Q[i])
+        x[q] = y[i] ^ (int(S[i, q + 1:].astype(np.int64) @ x[q + 1:].astype(np.int64)) & 1)
+    return x
+
+
+def kernel_basis(m: int, n: int, r: int, Q, Ap) -> np.ndarray:
+    """A basis of {x : A x = 0} as the rows of an (n - r) x n 0/1 array, one per
+    non-pivot column f: x[f] = 1, the other non-pivot entries 0, the pivot entries
+    from S x = 0 (L and P are invertible on the rows that matter, so A x = 0
+    exactly when S x = 0)."""
+    _, S = unpack_LS(Ap, m, n, r, Q)
+    piv = {int(q) for q in Q[:r]}
+    basis = []
+    for f in range(n):
+        if f in piv:
+            continue
+        x = np.zeros(n, dtype=np.uint8)
+        x[f] = 1
+        for i in range(r - 1, -1, -1):
+            q = int(Q[i])
+            x[q] = int(S[i, q + 1:].astype(np.int64) @ x[q + 1:].astype(np.int64)) & 1
+        basis.append(x)
+    return np.array(basis, dtype=np.uint8).reshape(len(basis), n)
