@@ -182,7 +182,7 @@ def main() -> int:
         def step(i):
             g.pls(copies[i], m, n, sch, ws=ws, P=P, Q=Q, rank=rank)
             if not args.no_rref:
-                g.rref(copies[i], m, n, Q, rank, R=R, ws=ws)
+                g.rref(copies[i], m, n, Q, rank, R=R, ws=ws, s=sch)
 
         for i in range(warmup):
             step(i)

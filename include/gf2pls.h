@@ -128,10 +128,15 @@ size_t gf2_rref_workspace_bytes(int64_t m, int64_t n);
  * A_pls, Q and rank are gf2_pls outputs (device); A_pls is only read.
  * R_out (m x n, same shape as A_pls, its own buffer) receives the RREF of the
  * original A: rows < r in reduced echelon form with leading ones at Q[0..r),
- * rows >= r zero.
+ * rows >= r zero.  With U = S[:, Q] (unit upper triangular), R = U^{-1} S: only
+ * the non-pivot columns need the triangular solve, which Section 5's reduction
+ * turns into products; they use the schedule's Schur variant (s == NULL: the
+ * default schedule; only the schur field is read).  Every extent depends on the
+ * rank, which is read on the device: the call enqueues a fixed kernel sequence
+ * sized for rank min(m, n), waits for nothing, and can be captured in a graph.
  */
 int gf2_rref(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int32_t *rank,
-             gf2_mat R_out, void *ws, size_t ws_bytes, void *stream);
+             gf2_mat R_out, const gf2_sched *s, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Batched PLS: `count` independent matrices of any shapes up to
@@ -253,10 +258,10 @@ int gf2_addmul(gf2_ctx *ctx, gf2_mat C, gf2_mat A, gf2_mat B, int variant,
 
 /*
  * Launch timing of the Schur-product kernels (diagnostics for roofline reports).
- * gf2_prof_enable: dev_log is a caller-owned DEVICE array of 2 * log_slots int32
+ * gf2_prof_enable: dev_log is a caller-owned DEVICE array of 3 * log_slots int32
  * (NULL disables).  While enabled, each product launch of gf2_pls / gf2_rref is
- * bracketed by HIP events on its stream and writes its row count M and inner
- * dimension K to the log (up to log_slots launches).
+ * bracketed by HIP events on its stream and writes its row count M, inner
+ * dimension K and column count N to the log (up to log_slots launches).
  * gf2_prof_read: waits for the recorded events, returns the launch count, the
  * summed event time and the summed algorithmic operations 2*M*N*K (one AND and
  * one XOR per bit product), then clears the record.

@@ -65,6 +65,8 @@ def _load():
         lib.oracle_rref.argtypes = [p, i64, i64, i64, p]
         lib.oracle_threads.restype = ctypes.c_int
         lib.oracle_threads.argtypes = []
+        lib.oracle_mul64.restype = None
+        lib.oracle_mul64.argtypes = [p, i64, i64, i64, p, p]
         _lib = lib
     return _lib
 
@@ -101,6 +103,22 @@ def rref(A: np.ndarray, m: int, n: int):
         return 0, a, piv[:0]
     r = _load().oracle_rref(a.ctypes.data, m, n, a.shape[1], piv.ctypes.data)
     return int(r), a, piv[:r].copy()
+
+
+def mul64(M: np.ndarray, rows: int, W: int, V: np.ndarray) -> np.ndarray:
+    """64 GF(2) matrix-vector products at once (checker for Freivalds' test):
+    bit t of out[i] = parity of popcount(M[i, :W] AND v_t), with bit t of V[j]
+    entry j of v_t (V: uint64[64 W])."""
+    if M.dtype != np.uint64 or M.ndim != 2 or M.shape[0] < rows or M.shape[1] < W:
+        raise ValueError("M must be uint64 (>= rows, >= W)")
+    V = np.ascontiguousarray(V, dtype=np.uint64)
+    if V.shape[0] < 64 * W:
+        raise ValueError("V needs 64 W entries")
+    M = np.ascontiguousarray(M)
+    out = np.zeros(max(rows, 1), dtype=np.uint64)
+    if rows > 0:
+        _load().oracle_mul64(M.ctypes.data, rows, W, M.shape[1], V.ctypes.data, out.ctypes.data)
+    return out[:rows]
 
 
 # ---------------------------------------------------------------- conversions

@@ -97,8 +97,8 @@ int64_t oracle_pls(uint64_t *A, int64_t m, int64_t n, int64_t stride, int32_t *P
 #else
         swap_rows(A, stride, r, pi);
 #endif
-        /* clear below but preserve the transformation matrix: the bit A[l][j]
-           stays (it is L[l][r]); addition starts at column j + 1 */
+        /* eliminate column j from the rows below; the one at A[l][j] is kept,
+           since it is the multiplier L[l][r], so the row sum starts at j + 1 */
         if (pj + 1 < n) {
             const int64_t rr = r, jj = pj;
 #pragma omp parallel for schedule(static) if ((m - rr) * (n - jj) > (1 << 22))
@@ -116,7 +116,8 @@ int64_t oracle_pls(uint64_t *A, int64_t m, int64_t n, int64_t stride, int32_t *P
     }
     for (int64_t i = r; i < m; i++) P[i] = (int32_t)i;
     for (int64_t i = r; i < n; i++) Q[i] = (int32_t)i;
-    /* compress L: swap columns j and Q[j] starting at row j */
+    /* compress L: the multipliers of pivot j sit in column Q[j]; exchange that
+       column with column j on rows j..m-1, which moves them next to each other */
     for (int64_t j = 0; j < r; j++) {
         int64_t q = Q[j];
         if (q == j) continue;
@@ -162,6 +163,29 @@ int64_t oracle_rref(uint64_t *A, int64_t m, int64_t n, int64_t stride, int32_t *
         r += 1;
     }
     return r;
+}
+
+/*
+ * Checker for randomized tests (Freivalds 1977), 64 random vectors at once:
+ * out[i] bit t = parity of popcount(M[i] AND v_t) over words [0, W) of row i,
+ * where bit t of V[j] is entry j of vector v_t (V has 64 W entries).
+ */
+void oracle_mul64(const uint64_t *M, int64_t rows, int64_t W, int64_t stride, const uint64_t *V,
+                  uint64_t *out)
+{
+#pragma omp parallel for schedule(static) if (rows * W > (1 << 16))
+    for (int64_t i = 0; i < rows; i++) {
+        const uint64_t *row = M + i * stride;
+        uint64_t acc = 0;
+        for (int64_t w = 0; w < W; w++) {
+            uint64_t x = row[w];
+            while (x) {
+                acc ^= V[64 * w + __builtin_ctzll(x)];
+                x &= x - 1;
+            }
+        }
+        out[i] = acc;
+    }
 }
 
 /* Number of OpenMP threads the oracle would use (1 when built without OpenMP). */

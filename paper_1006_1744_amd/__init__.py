@@ -87,7 +87,7 @@ def _load():
     L.gf2_pls_unpack.restype = i32
     L.gf2_rref_workspace_bytes.argtypes = [i64, i64]
     L.gf2_rref_workspace_bytes.restype = sz
-    L.gf2_rref.argtypes = [vp, Mat, vp, vp, Mat, vp, sz, vp]
+    L.gf2_rref.argtypes = [vp, Mat, vp, vp, Mat, ctypes.POINTER(Sched), vp, sz, vp]
     L.gf2_rref.restype = i32
     L.gf2_pls_batched_workspace_bytes.argtypes = [i64]
     L.gf2_pls_batched_workspace_bytes.restype = sz
@@ -422,15 +422,18 @@ def rref_workspace_bytes(m: int, n: int) -> int:
 
 
 def rref(A_pls: torch.Tensor, m: int, n: int, Q: torch.Tensor, rank: torch.Tensor,
-         R: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None):
-    """RREF of the original matrix from its PLS; returns R (m, stride) int64."""
+         R: torch.Tensor | None = None, ws: torch.Tensor | None = None, s: Sched | None = None,
+         stream=None):
+    """RREF of the original matrix from its PLS; returns R (m, stride) int64.
+    The triangular solve's products use s.schur (None: the default schedule)."""
     dev = A_pls.device
     R = torch.empty_like(A_pls) if R is None else R
     nb = rref_workspace_bytes(m, n)
     if ws is None or ws.numel() < nb:
         ws = workspace(nb, dev)
     _check(get_lib().gf2_rref(ctx(dev.index), _mat(A_pls, m, n), Q.data_ptr(), rank.data_ptr(),
-                        _mat(R, m, n), ws.data_ptr(), ws.numel(), _stream(stream)))
+                              _mat(R, m, n), ctypes.byref(s) if s is not None else None,
+                              ws.data_ptr(), ws.numel(), _stream(stream)))
     return R
 
 
@@ -452,7 +455,7 @@ _prof_logs = {}
 def prof_enable(slots: int = 1 << 16, device=None):
     """Time every Schur-product launch with HIP events (see gf2_prof_enable)."""
     dev = torch.cuda.current_device() if device is None else device
-    log = torch.zeros(2 * slots, dtype=torch.int32, device=f"cuda:{dev}")
+    log = torch.zeros(3 * slots, dtype=torch.int32, device=f"cuda:{dev}")
     _prof_logs[dev] = log
     _check(get_lib().gf2_prof_enable(ctx(dev), log.data_ptr(), slots))
 

@@ -21,13 +21,15 @@
 #include "gf2_internal.h"
 
 // Optional per-launch timing of the product kernels: events recorded on the
-// launch stream around each launch, the kernel storing its dynamic M and K in a
-// caller-provided device log.
+// launch stream around each launch, the kernel storing its dynamic M, K and N in
+// a caller-provided device log.
 struct ProfRec {
     hipEvent_t a, b;
     int slot;
-    int ncols;
 };
+
+// ints per launch in the device log: M, K and the column count N
+constexpr int kProfInts = 3;
 
 struct gf2_ctx {
     int device;
@@ -87,11 +89,12 @@ hipEvent_t pool_event(gf2_ctx *ctx, size_t idx) {
 
 // pre_transposed: Bt already holds B transposed (kmax <= kMfmaMaxK, row stride
 // (kmax + 63) / 64 words, rows past K zero), so no transpose is launched.
+// nwd (nullable, device): dynamic number of C words, at most nw.
 hipError_t enqueue_gemm(gf2_ctx *ctx, uint64_t *C, int64_t sc, const uint64_t *Am, int64_t sa,
                         const uint64_t *Bsrc, int64_t sb, int m, int kmrows, RowRange crows,
                         int aw, int cw, int nw, RowRange brows, int kmax, int schur,
                         const int32_t *rk, uint64_t *Bt, hipStream_t st,
-                        bool pre_transposed = false) {
+                        bool pre_transposed = false, const int32_t *nwd = nullptr) {
     if (pre_transposed && kmax > kMfmaMaxK) return hipErrorInvalidValue;
     for (int k0 = 0; k0 < kmax; k0 += kMfmaMaxK) {
         const int kc = std::min(kMfmaMaxK, kmax - k0);
@@ -100,26 +103,26 @@ hipError_t enqueue_gemm(gf2_ctx *ctx, uint64_t *C, int64_t sc, const uint64_t *A
         br.s = std::min(br.s - k0, kc);
         const int64_t sbt = (kc + 63) / 64;
         hipError_t e = hipSuccess;
-        if (!pre_transposed) e = launch_transpose(Bsrc, sb, kmrows, br, cw, nw, kc, Bt, sbt, rk, st);
+        if (!pre_transposed)
+            e = launch_transpose(Bsrc, sb, kmrows, br, cw, nw, kc, Bt, sbt, rk, st, nwd);
         if (e != hipSuccess) return e;
         int32_t *plog = nullptr;
         ProfRec rec{};
         const bool prof = ctx && ctx->plog && (int64_t)ctx->recs.size() < ctx->plog_cap;
         if (prof) {
             rec.slot = (int)ctx->recs.size();
-            rec.ncols = 64 * nw;
             rec.a = pool_event(ctx, 2 * (size_t)rec.slot);
             rec.b = pool_event(ctx, 2 * (size_t)rec.slot + 1);
             if (!rec.a || !rec.b) return hipErrorOutOfMemory;
-            plog = ctx->plog + 2 * rec.slot;
+            plog = ctx->plog + kProfInts * rec.slot;
             if ((e = hipEventRecord(rec.a, st)) != hipSuccess) return e;
         }
         if (schur == GF2_SCHUR_MFMA || schur == GF2_SCHUR_FP4)
             e = launch_gemm_mfma(C, sc, Am, sa, m, crows, aw + k0 / 64, cw, nw, Bt, sbt, kc, br,
-                                 kmrows, rk, plog, schur == GF2_SCHUR_FP4, st);
+                                 kmrows, rk, plog, schur == GF2_SCHUR_FP4, st, nwd);
         else
             e = launch_gemm_xor(C, sc, Am, sa, m, crows, aw + k0 / 64, cw, nw, Bt, sbt, kc, br,
-                                kmrows, rk, plog, st);
+                                kmrows, rk, plog, st, nwd);
         if (e != hipSuccess) return e;
         if (prof) {
             if ((e = hipEventRecord(rec.b, st)) != hipSuccess) return e;
@@ -366,7 +369,7 @@ int gf2_prof_read_launches(gf2_ctx *ctx, gf2_prof_launch *out, int64_t max, int6
     if (ctx->recs.empty()) return GF2_OK;
     if (hipSetDevice(ctx->device) != hipSuccess) return GF2_E_HIP;
     if (hipEventSynchronize(ctx->recs.back().b) != hipSuccess) return GF2_E_HIP;
-    std::vector<int32_t> log(2 * ctx->recs.size());
+    std::vector<int32_t> log(kProfInts * ctx->recs.size());
     if (hipMemcpy(log.data(), ctx->plog, log.size() * sizeof(int32_t), hipMemcpyDeviceToHost) !=
         hipSuccess)
         return GF2_E_HIP;
@@ -376,9 +379,9 @@ int gf2_prof_read_launches(gf2_ctx *ctx, gf2_prof_launch *out, int64_t max, int6
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return GF2_E_HIP;
         out[k].ms = ms;
-        out[k].m = log[2 * r.slot];
-        out[k].n = r.ncols;
-        out[k].k = log[2 * r.slot + 1];
+        out[k].m = log[kProfInts * r.slot];
+        out[k].k = log[kProfInts * r.slot + 1];
+        out[k].n = log[kProfInts * r.slot + 2];
         k++;
     }
     *count = k;
@@ -393,7 +396,7 @@ int gf2_prof_read(gf2_ctx *ctx, gf2_prof_stats *out) {
     if (ctx->recs.empty()) return GF2_OK;
     if (hipSetDevice(ctx->device) != hipSuccess) return GF2_E_HIP;
     if (hipEventSynchronize(ctx->recs.back().b) != hipSuccess) return GF2_E_HIP;
-    std::vector<int32_t> log(2 * ctx->recs.size());
+    std::vector<int32_t> log(kProfInts * ctx->recs.size());
     if (hipMemcpy(log.data(), ctx->plog, log.size() * sizeof(int32_t), hipMemcpyDeviceToHost) !=
         hipSuccess)
         return GF2_E_HIP;
@@ -403,8 +406,8 @@ int gf2_prof_read(gf2_ctx *ctx, gf2_prof_stats *out) {
         if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return GF2_E_HIP;
         out->launches += 1;
         out->total_ms += ms;
-        out->total_ops += 2.0 * (double)log[2 * r.slot] * (double)r.ncols *
-                          (double)log[2 * r.slot + 1];
+        out->total_ops += 2.0 * (double)log[kProfInts * r.slot] *
+                          (double)log[kProfInts * r.slot + 2] * (double)log[kProfInts * r.slot + 1];
     }
     ctx->recs.clear();
     return GF2_OK;
@@ -524,15 +527,20 @@ int gf2_pls_batched(gf2_ctx *ctx, const gf2_batch_item *items, int64_t count, in
 }  // extern "C"
 
 namespace {
+// Workspace of gf2_rref.  Every extent of the solve depends on the rank, which
+// only the device knows: `rr` holds {0, r, ceil((n - r) / 64)} (written by the
+// first kernel), and every later launch is sized for the largest possible rank
+// rmax = min(m, n) and clipped to rr on the device.
 struct RrefLayout {
     size_t rr, pm, nm, pp, pn, uc, xc, bt, total;
     int64_t su, sx;
-    int rmax;
+    int rmax, nw;
 };
 
 RrefLayout rref_layout(int64_t m, int64_t n) {
     RrefLayout L;
     const int64_t nw = std::max<int64_t>((n + 63) / 64, 1);
+    L.nw = (int)nw;
     L.rmax = (int)std::min(m, n);
     L.su = std::max<int64_t>((L.rmax + 63) / 64, 1);
     L.sx = nw;
@@ -550,13 +558,19 @@ RrefLayout rref_layout(int64_t m, int64_t n) {
     return L;
 }
 
+// X <- U^{-1} X for the unit upper triangular U (r x r, rows of Uc) on the
+// compact non-pivot block X (r rows, rr[2] words): recursive on row halves,
+// the lower half first, the coupling block by one product (Section 5 reduces
+// the triangular solve to products), blocks of up to 1024 rows by the blocked
+// table solve.  Launched for rmax rows and nwmax words; the kernels clip both
+// to rr on the device.
 struct UpperSolve {
     gf2_ctx *ctx;
     uint64_t *X;
     int64_t sx;
     const uint64_t *U;
     int64_t su;
-    int r, nwx;
+    int rmax, nwmax, schur;
     const int32_t *rr;
     uint64_t *Bt;
     hipStream_t st;
@@ -566,18 +580,17 @@ struct UpperSolve {
     }
     // rows [a, min(r, a + sz)) <- U^{-1} rows, solving the last rows first
     void solve(int a, int sz) {
-        if (a >= r || sz <= 0) return;
+        if (a >= rmax || sz <= 0) return;
         if (sz <= trsm_block_max_rows()) {
-            chk(launch_trsm_block(X, sx, U, su, r, row_range(-1, -1, a, sz), a / 64, 0, nwx, rr, 0,
-                                  (sz + 63) / 64, nullptr, nullptr, 0, 0, st));
+            chk(launch_trsm_block(X, sx, U, su, rmax, row_range(-1, 1, a, sz), a / 64, 0, nwmax, rr,
+                                  0, (sz + 63) / 64, nullptr, nullptr, 0, 0, st, rr + 2));
             return;
         }
         const int h = (sz / 64 / 2) * 64;
         solve(a + h, sz - h);
-        if (a + h < r)
-            chk(enqueue_gemm(ctx, X, sx, U, su, X, sx, r, r, row_range(-1, -1, a, h), (a + h) / 64, 0,
-                             nwx, row_range(-1, -1, a + h, sz - h), sz - h, GF2_SCHUR_MFMA, rr,
-                             Bt, st));
+        chk(enqueue_gemm(ctx, X, sx, U, su, X, sx, rmax, rmax, row_range(-1, 1, a, h), (a + h) / 64,
+                         0, nwmax, row_range(-1, 1, a + h, sz - h), sz - h, schur, rr, Bt, st,
+                         false, rr + 2));
         solve(a, h);
     }
 };
@@ -589,7 +602,8 @@ extern "C" size_t gf2_rref_workspace_bytes(int64_t m, int64_t n) {
 }
 
 extern "C" int gf2_rref(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int32_t *rank,
-                        gf2_mat R_out, void *ws, size_t ws_bytes, void *stream) {
+                        gf2_mat R_out, const gf2_sched *s, void *ws, size_t ws_bytes,
+                        void *stream) {
     if (!ctx) return GF2_E_ARG;
     int rc;
     if ((rc = check_mat(A_pls)) != GF2_OK) return rc;
@@ -597,6 +611,8 @@ extern "C" int gf2_rref(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int
     if (R_out.m != A_pls.m || R_out.n != A_pls.n) return GF2_E_ARG;
     if (!rank || (A_pls.n > 0 && !Q)) return GF2_E_ARG;
     if (R_out.words == A_pls.words && A_pls.m > 0) return GF2_E_ARG;
+    const gf2_sched ss = s ? *s : default_sched();
+    if (!sched_ok(&ss)) return GF2_E_ARG;
     RrefLayout L = rref_layout(A_pls.m, A_pls.n);
     if (!ws || ws_bytes < L.total) return GF2_E_WORKSPACE;
     if (((uintptr_t)ws & 255) != 0) return GF2_E_ALIGN;
@@ -605,31 +621,24 @@ extern "C" int gf2_rref(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int
     hipStream_t st = (hipStream_t)stream;
     char *base = (char *)ws;
     const int m = (int)A_pls.m, n = (int)A_pls.n;
+    int32_t *rr = (int32_t *)(base + L.rr);
     uint64_t *PM = (uint64_t *)(base + L.pm), *NM = (uint64_t *)(base + L.nm);
     int32_t *pp = (int32_t *)(base + L.pp), *pn = (int32_t *)(base + L.pn);
     uint64_t *Uc = (uint64_t *)(base + L.uc), *Xc = (uint64_t *)(base + L.xc);
-    GF2_TRY(launch_rref_masks(PM, NM, pp, pn, Q, rank, n, L.rmax, st));
-    // the rank fixes every extent below: read it once
-    int32_t r = 0;
-    GF2_TRY(hipMemcpyAsync(&r, rank, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    GF2_TRY(hipStreamSynchronize(st));
-    if (r < 0 || r > L.rmax) return GF2_E_ARG;
-    const int nwx = (n - r + 63) / 64;
-    // with no non-pivot column (r == n) R is the pivot pattern alone: nothing to
-    // gather or solve
-    if (r > 0 && nwx > 0) {
-        GF2_TRY(launch_zero_rows(Uc, L.su, r, (r + 63) / 64, st));
-        GF2_TRY(launch_zero_rows(Xc, L.sx, r, nwx, st));
-        GF2_TRY(launch_rref_gather(A_pls.words, A_pls.stride, Q, r, n, PM, NM, pp, pn, Uc, L.su,
-                                   Xc, L.sx, st));
-        UpperSolve us;
-        us.ctx = ctx;
-        us.X = Xc; us.sx = L.sx; us.U = Uc; us.su = L.su; us.r = r; us.nwx = nwx;
-        us.rr = (const int32_t *)(base + L.rr); us.Bt = (uint64_t *)(base + L.bt); us.st = st;
-        us.solve(0, (r + 63) / 64 * 64);
-        if (us.err != hipSuccess) return GF2_E_HIP;
-    }
-    GF2_TRY(launch_rref_scatter(R_out.words, R_out.stride, m, n, Q, r, NM, pn, Xc, L.sx, st));
+    GF2_TRY(launch_rref_masks(PM, NM, pp, pn, Q, rank, n, L.rmax, rr, st));
+    // with no non-pivot column (r == n) every kernel below returns at once: R is
+    // the pivot pattern alone
+    GF2_TRY(launch_rref_zero(Uc, L.su, Xc, L.sx, L.rmax, rr, st));
+    GF2_TRY(launch_rref_gather(A_pls.words, A_pls.stride, Q, L.rmax, n, PM, NM, pp, pn, Uc, L.su, Xc,
+                               L.sx, rr, st));
+    UpperSolve us;
+    us.ctx = ctx;
+    us.X = Xc; us.sx = L.sx; us.U = Uc; us.su = L.su;
+    us.rmax = L.rmax; us.nwmax = L.nw; us.schur = ss.schur;
+    us.rr = rr; us.Bt = (uint64_t *)(base + L.bt); us.st = st;
+    us.solve(0, (L.rmax + 63) / 64 * 64);
+    if (us.err != hipSuccess) return GF2_E_HIP;
+    GF2_TRY(launch_rref_scatter(R_out.words, R_out.stride, m, n, Q, rr, NM, pn, Xc, L.sx, st));
     // zero the padding words of R past ceil(n/64)
     const int nw = (n + 63) / 64;
     if (R_out.stride > nw)

@@ -68,14 +68,6 @@ hipError_t launch_leaf(uint64_t *A, int64_t stride, uint64_t *Ab, int64_t sb, in
 size_t panel_info_bytes();
 size_t panel_info_linv_offset();
 
-// X <- L^{-1} X for at most 64 rows `rows` of X (matrix A) with the unit lower
-// triangular L taken from word column lw of the same rows of matrix Lm (bit i
-// of the block's row i is the diagonal), on word columns [w_lo, w_hi) of A.
-// lower = 0 solves with the unit upper triangle (bits > i) instead.
-hipError_t launch_trsm_base(uint64_t *A, int64_t stride, const uint64_t *Lm, int64_t sl, int m,
-                            RowRange rows, int lw, int w_lo, int w_hi, const int32_t *rk,
-                            int lower, hipStream_t st);
-
 // X <- T^{-1} X for up to nbmax (<= trsm_block_max_rows() / 64) blocks of 64 rows
 // `rows` of A; T's rows are the same rows of Lm, the block of 64 columns starting
 // at word lw0 (diagonal block b at word lw0 + b).  lower = 0: unit upper.
@@ -86,7 +78,7 @@ hipError_t launch_trsm_base(uint64_t *A, int64_t stride, const uint64_t *Lm, int
 hipError_t launch_trsm_block(uint64_t *A, int64_t stride, const uint64_t *Lm, int64_t sl, int m,
                              RowRange rows, int lw0, int w_lo, int w_hi, const int32_t *rk,
                              int lower, int nbmax, const uint64_t *linv_store, uint64_t *Bt,
-                             int64_t sbt, int kw0, hipStream_t st);
+                             int64_t sbt, int kw0, hipStream_t st, const int32_t *nwd = nullptr);
 int trsm_block_max_rows();
 
 // Table-driven update after a panel (Section 4.1: MakeTable1 / AddRowsFromTable)
@@ -119,35 +111,42 @@ hipError_t launch_finalize(int32_t *P, int32_t *Q, int32_t *rank, const int32_t 
 // Bit transpose: Bt (rows = 64 * nw bits of B's columns, words = ceil(kmax/64))
 // from B rows `brows` (K = their count), word columns [w_lo, w_lo + nw).
 // Rows of B beyond K read as zero.
+// nwd (nullable, device): a dynamic word count; the launch covers
+// min(nw, *nwd) words (the same in the products and the blocked solve below).
 hipError_t launch_transpose(const uint64_t *B, int64_t sb, int m, RowRange brows, int w_lo,
                             int nw, int kmax, uint64_t *Bt, int64_t sbt, const int32_t *rk,
-                            hipStream_t st);
+                            hipStream_t st, const int32_t *nwd = nullptr);
 
 // C[rows, words w_lo..w_lo+nw) ^= A[rows, K bits from word aw] * B, with B given
 // transposed in Bt (64*nw rows of kmax bits, zero past K).  K is the length of
 // krows evaluated with kmrows as the default end.
-// prof (nullable): the kernel stores its M and K there (timing diagnostics).
+// prof (nullable): the kernel stores its M, K and column count there (timing
+// diagnostics).
 hipError_t launch_gemm_xor(uint64_t *C, int64_t sc, const uint64_t *A, int64_t sa, int m,
                            RowRange rows, int aw, int w_lo, int nw, const uint64_t *Bt,
                            int64_t sbt, int kmax, RowRange krows, int kmrows, const int32_t *rk,
-                           int32_t *prof, hipStream_t st);
+                           int32_t *prof, hipStream_t st, const int32_t *nwd = nullptr);
 hipError_t launch_gemm_mfma(uint64_t *C, int64_t sc, const uint64_t *A, int64_t sa, int m,
                             RowRange rows, int aw, int w_lo, int nw, const uint64_t *Bt,
                             int64_t sbt, int kmax, RowRange krows, int kmrows, const int32_t *rk,
-                            int32_t *prof, bool fp4, hipStream_t st);
+                            int32_t *prof, bool fp4, hipStream_t st,
+                            const int32_t *nwd = nullptr);
 
-// RREF helpers (k_rref.hip)
+// RREF helpers (k_rref.hip).  rr (device int32[3]) = {0, r, ceil((n - r) / 64)}
+// is written by launch_rref_masks from *rank; the others read r from it.
 hipError_t launch_zero_rows(uint64_t *X, int64_t sx, int rows, int words, hipStream_t st);
 hipError_t launch_rref_masks(uint64_t *PM, uint64_t *NM, int32_t *prefP, int32_t *prefN,
-                             const int32_t *Q, const int32_t *rank, int n, int rmax,
+                             const int32_t *Q, const int32_t *rank, int n, int rmax, int32_t *rr,
                              hipStream_t st);
-hipError_t launch_rref_gather(const uint64_t *Ap, int64_t sap, const int32_t *Q, int r, int n,
+hipError_t launch_rref_zero(uint64_t *Uc, int64_t su, uint64_t *Xc, int64_t sx, int rmax,
+                            const int32_t *rr, hipStream_t st);
+hipError_t launch_rref_gather(const uint64_t *Ap, int64_t sap, const int32_t *Q, int rmax, int n,
                               const uint64_t *PM, const uint64_t *NM, const int32_t *prefP,
                               const int32_t *prefN, uint64_t *Uc, int64_t su, uint64_t *Xc,
-                              int64_t sx, hipStream_t st);
-hipError_t launch_rref_scatter(uint64_t *R, int64_t sr, int m, int n, const int32_t *Q, int r,
-                               const uint64_t *NM, const int32_t *prefN, const uint64_t *Xc,
-                               int64_t sx, hipStream_t st);
+                              int64_t sx, const int32_t *rr, hipStream_t st);
+hipError_t launch_rref_scatter(uint64_t *R, int64_t sr, int m, int n, const int32_t *Q,
+                               const int32_t *rr, const uint64_t *NM, const int32_t *prefN,
+                               const uint64_t *Xc, int64_t sx, hipStream_t st);
 
 // Batched PLS (k_batch.hip): queue order, then one persistent launch of `grid`
 // blocks.  ws holds batch_ws_bytes(count) bytes.

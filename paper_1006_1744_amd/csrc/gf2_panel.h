@@ -43,11 +43,6 @@ struct PanelInfo {
     uint64_t u[64];  // pivot rows' panel words when chosen (reduced by earlier pivots)
     uint64_t linv[64];  // rows of L^{-1} for the panel's r x r unit lower triangle
     int32_t moved[kMovedInts];
-#ifdef GF2_TRACE
-    uint64_t trace[24];
-    uint64_t trace_post[8];
-    uint64_t trace_upd[8];
-#endif
 };
 
 // Build tables for pivots [ta, tb) (consecutive columns q[ta], q[ta]+1, ...):
@@ -173,13 +168,6 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
     const int NOHIT = 0x7fffffff;
     bool simple = true;      // one window, no far search: moves read off sOg[]
 
-#ifdef GF2_TRACE
-    int ntr = 0;
-#define TR() do { if (tid == 0 && ntr < 22) { info->trace[ntr++] = __builtin_amdgcn_s_memrealtime(); info->trace[ntr++] = __builtin_amdgcn_s_memtime(); } } while (0)
-#else
-#define TR() do {} while (0)
-#endif
-    TR();
     if (tid == 0) {
         s_t = 0; s_c = 0; s_F = 0; s_pa = 0; s_tab_lo = -1; s_tab_hi = -1; s_brk = 0;
         s_far = NOHIT; s_epochs = 0;
@@ -214,9 +202,7 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
             }
             int og0 = o0, og1 = o1;
             uint64_t m0 = __ballot(o0 < mrem), m1 = __ballot(o1 < mrem);   // candidates
-            TR();
             uint64_t c0 = transpose64(x0, lane), c1 = transpose64(x1, lane);
-            TR();
             int fer = -1;   // lane j: window entry of the pivot of column j (this epoch)
             // loop state kept in scalar registers: column, pivot count, candidates
             int cc = __builtin_amdgcn_readfirstlane(c);
@@ -292,12 +278,10 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
                 brk = 1;
                 break;
             }
-            TR();
             x0 = transpose64(c0, lane);
             x1 = transpose64(c1, lane);
             if (o0 < mrem) col[(int64_t)o0 * stride] = x0;
             if (o1 < mrem) col[(int64_t)o1 * stride] = x1;
-            TR();
             // bookkeeping of the pivots [t, tt), one lane per column
             const uint64_t isp = __ballot(fer >= 0);
             if (fer >= 0) {
@@ -404,7 +388,6 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
     }
     __syncthreads();
 
-    TR();
     const int r = max(0, min(s_t, mrem));
     if (wave == 0) {
         int32_t *mv = info->moved;
@@ -457,7 +440,6 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
             if (lane < nk) { mv[1 + 2 * lane] = pos0; mv[2 + 2 * lane] = src0; }
             if (lane + 64 < nk) { mv[1 + 2 * (lane + 64)] = pos1; mv[2 + 2 * (lane + 64)] = src1; }
         }
-        TR();
         const int ru = __builtin_amdgcn_readfirstlane(r);
         const uint64_t urow = lane < ru ? sU[lane] : 0ull;
         const int qv = lane < ru ? sQ[lane] : lane;
@@ -476,10 +458,6 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
             info->compress = moved_cols != 0;
         }
     }
-    TR();
-#ifdef GF2_TRACE
-    if (tid == 0) info->trace[23] = ntr;
-#endif
     __syncthreads();
     return r;
 }

@@ -18,7 +18,8 @@ namespace gf2 {
 __global__ __launch_bounds__(256) void transpose_direct_kernel(const uint64_t *B, int64_t sb, int m,
                                                                RowRange brows, int w_lo, int nw,
                                                                int kmax, uint64_t *Bt, int64_t sbt,
-                                                               const int32_t *rk) {
+                                                               const int32_t *rk, const int32_t *nwd) {
+    if (nwd) nw = min(nw, *nwd);
     int b0, b1;
     eval_range(rk, m, brows, b0, b1);
     const int K = b1 - b0;
@@ -46,8 +47,9 @@ constexpr int TP_JW = 16;
 __global__ __launch_bounds__(256) void transpose_kernel(const uint64_t *B, int64_t sb, int m,
                                                         RowRange brows, int w_lo, int nw, int kmax,
                                                         uint64_t *Bt, int64_t sbt,
-                                                        const int32_t *rk) {
+                                                        const int32_t *rk, const int32_t *nwd) {
     __shared__ uint64_t sT[64][TP_JW + 1];
+    if (nwd) nw = min(nw, *nwd);
     int b0, b1;
     eval_range(rk, m, brows, b0, b1);
     const int K = b1 - b0;
@@ -78,20 +80,20 @@ __global__ __launch_bounds__(256) void transpose_kernel(const uint64_t *B, int64
 
 hipError_t launch_transpose(const uint64_t *B, int64_t sb, int m, RowRange brows, int w_lo,
                             int nw, int kmax, uint64_t *Bt, int64_t sbt, const int32_t *rk,
-                            hipStream_t st) {
+                            hipStream_t st, const int32_t *nwd) {
     const int nkw = (kmax + 63) / 64;
     if ((int64_t)nkw * nw <= 0) return hipSuccess;
     if ((int64_t)nkw * nw < 16384) {
         const int64_t blocks = ((int64_t)nkw * nw + 3) / 4;
         hipLaunchKernelGGL(transpose_direct_kernel, dim3((unsigned)blocks), dim3(256), 0, st, B, sb,
-                           m, brows, w_lo, nw, kmax, Bt, sbt, rk);
+                           m, brows, w_lo, nw, kmax, Bt, sbt, rk, nwd);
         return hipGetLastError();
     }
     const int64_t total = (int64_t)nkw * ((nw + TP_JW - 1) / TP_JW);
     int64_t blocks = total < 2048 ? total : 2048;
     if (blocks >= 8) blocks = blocks / 8 * 8;
     hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)blocks), dim3(256), 0, st, B, sb, m, brows,
-                       w_lo, nw, kmax, Bt, sbt, rk);
+                       w_lo, nw, kmax, Bt, sbt, rk, nwd);
     return hipGetLastError();
 }
 
@@ -106,9 +108,10 @@ __global__ __launch_bounds__(256) void gemm_xor_kernel(uint64_t *C, int64_t sc, 
                                                        int w_lo, int nw, const uint64_t *Bt,
                                                        int64_t sbt, int nkw, RowRange krows,
                                                        int kmrows, const int32_t *rk,
-                                                       int32_t *prof) {
+                                                       int32_t *prof, const int32_t *nwd) {
     __shared__ uint64_t sA[GX_TM][GX_LD];
     __shared__ uint64_t sB[GX_TNW * 64][GX_LD];
+    if (nwd) nw = min(nw, *nwd);
     int r0, r1;
     eval_range(rk, m, rows, r0, r1);
     const int M = r1 - r0;
@@ -117,8 +120,9 @@ __global__ __launch_bounds__(256) void gemm_xor_kernel(uint64_t *C, int64_t sc, 
     if (prof && blockIdx.x == 0 && threadIdx.x == 0) {
         prof[0] = M;
         prof[1] = k1 - k0;
+        prof[2] = 64 * max(nw, 0);
     }
-    if (M <= 0) return;
+    if (M <= 0 || nw <= 0) return;
     nkw = min(nkw, (k1 - k0 + 63) / 64);
     if (nkw <= 0) return;
     const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
@@ -212,14 +216,14 @@ __global__ __launch_bounds__(256) void gemm_xor_kernel(uint64_t *C, int64_t sc, 
 hipError_t launch_gemm_xor(uint64_t *C, int64_t sc, const uint64_t *A, int64_t sa, int m,
                            RowRange rows, int aw, int w_lo, int nw, const uint64_t *Bt,
                            int64_t sbt, int kmax, RowRange krows, int kmrows, const int32_t *rk,
-                           int32_t *prof, hipStream_t st) {
+                           int32_t *prof, hipStream_t st, const int32_t *nwd) {
     int nkw = (kmax + 63) / 64;
     if (nw <= 0 || nkw <= 0) return hipSuccess;
     int64_t tiles = (int64_t)((m + GX_TM - 1) / GX_TM) * ((nw + GX_TNW - 1) / GX_TNW);
     int64_t blocks = tiles < 2048 ? tiles : 2048;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(gemm_xor_kernel, dim3((unsigned)blocks), dim3(256), 0, st, C, sc, A, sa, m,
-                       rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof);
+                       rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof, nwd);
     return hipGetLastError();
 }
 

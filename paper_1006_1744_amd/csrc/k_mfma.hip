@@ -111,12 +111,14 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
                                                        RowRange rows, int aw, int w_lo, int nw,
                                                        const uint64_t *Bt, int64_t sbt, int nkw,
                                                        RowRange krows, int kmrows,
-                                                       const int32_t *rk, int32_t *prof) {
+                                                       const int32_t *rk, int32_t *prof,
+                                                       const int32_t *nwd) {
     constexpr int TM = 64 * WT;             // block tile rows = columns
     constexpr int CPW = TM / 64;            // 1 KiB chunks per wave per operand and stage
     constexpr int STAGE = TM * G2_KC;       // words per operand per stage
     __shared__ __attribute__((aligned(16))) uint64_t sA[NB][STAGE];
     __shared__ __attribute__((aligned(16))) uint64_t sB[NB][STAGE];
+    if (nwd) nw = min(nw, *nwd);
     int r0, r1;
     eval_range(rk, m, rows, r0, r1);
     const int M = r1 - r0;
@@ -125,8 +127,9 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
     if (prof && blockIdx.x == 0 && threadIdx.x == 0) {
         prof[0] = M;
         prof[1] = k1 - k0;
+        prof[2] = 64 * max(nw, 0);
     }
-    if (M <= 0) return;
+    if (M <= 0 || nw <= 0) return;
     nkw = min(nkw, (k1 - k0 + 63) / 64);
     if (nkw <= 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -389,7 +392,7 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
 hipError_t launch_gemm_mfma(uint64_t *C, int64_t sc, const uint64_t *A, int64_t sa, int m,
                             RowRange rows, int aw, int w_lo, int nw, const uint64_t *Bt,
                             int64_t sbt, int kmax, RowRange krows, int kmrows, const int32_t *rk,
-                            int32_t *prof, bool fp4, hipStream_t st) {
+                            int32_t *prof, bool fp4, hipStream_t st, const int32_t *nwd) {
     int nkw = (kmax + 63) / 64;
     if (nw <= 0 || nkw <= 0) return hipSuccess;
     // 256 x 256 tiles pay off once the inner dimension is long enough to
@@ -404,10 +407,10 @@ hipError_t launch_gemm_mfma(uint64_t *C, int64_t sc, const uint64_t *A, int64_t 
         if (blocks < 1) blocks = 1;
         if (fp4)
             hipLaunchKernelGGL((gemm_dma_kernel<4, 3, true>), dim3((unsigned)blocks), dim3(256), 0, st, C,
-                               sc, A, sa, m, rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof);
+                               sc, A, sa, m, rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof, nwd);
         else
             hipLaunchKernelGGL((gemm_dma_kernel<4, 3, false>), dim3((unsigned)blocks), dim3(256), 0, st, C,
-                               sc, A, sa, m, rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof);
+                               sc, A, sa, m, rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof, nwd);
         return hipGetLastError();
     }
     // three blocks per CU (48 KiB of LDS each)
@@ -417,10 +420,10 @@ hipError_t launch_gemm_mfma(uint64_t *C, int64_t sc, const uint64_t *A, int64_t 
     if (blocks < 1) blocks = 1;
     if (fp4)
         hipLaunchKernelGGL((gemm_dma_kernel<2, 3, true>), dim3((unsigned)blocks), dim3(256), 0, st, C, sc,
-                           A, sa, m, rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof);
+                           A, sa, m, rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof, nwd);
     else
         hipLaunchKernelGGL((gemm_dma_kernel<2, 3, false>), dim3((unsigned)blocks), dim3(256), 0, st, C, sc,
-                           A, sa, m, rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof);
+                           A, sa, m, rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof, nwd);
     return hipGetLastError();
 }
 

@@ -14,9 +14,6 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
     // search's critical path: nothing reads it before the table update
     const int r = panel_search(A, stride, m, n, wc, R, P, Q, info, S, nullptr, false);
     if (threadIdx.x == 0) rk[b + 1] = R + r;
-#ifdef GF2_TRACE
-    if (threadIdx.x == 0) info->trace[20] = __builtin_amdgcn_s_memrealtime();
-#endif
 }
 
 // Final pass over the panel (blocks [0, nfin)) and the other word columns of
@@ -48,12 +45,6 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
     const int R = rk[b];
     const int mrem = m - R;
     if (mrem <= 0) return;
-#ifdef GF2_TRACE
-#define TRP(i) do { if (threadIdx.x == 0 && (blockIdx.x == 0 || (int)blockIdx.x == nfin)) const_cast<PanelInfo *>(info)->trace_post[(i) + ((int)blockIdx.x == nfin ? 4 : 0)] = __builtin_amdgcn_s_memrealtime(); } while (0)
-#else
-#define TRP(i) do {} while (0)
-#endif
-    TRP(0);
     const int r = info->r, F = info->F, pa = info->pa, cmp = info->compress;
     if (blockIdx.x == gridDim.x - 1) {
         if (tid < 64) {
@@ -72,10 +63,8 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
             sQ[tid] = info->q[tid];
         }
         __syncthreads();
-        TRP(1);
         if (pend) build_tables<POST_THREADS>(sU, sQ, pa, r, sT, tid);
         __syncthreads();
-        TRP(2);
         uint64_t *col = Ab + (int64_t)R * sb + wc;   // the panel word lies in the block
         const int step = nfin * POST_THREADS * POST_ROWS;
         for (int base = blockIdx.x * POST_THREADS * POST_ROWS; base < mrem; base += step) {
@@ -105,7 +94,6 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
                 if (w != v[u]) col[(int64_t)o * sb] = w;
             }
         }
-        TRP(3);
         return;
     }
     const int32_t *mv = info->moved;
@@ -117,7 +105,6 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
     }
     if (tid < 64) sPk[tid] = -1;
     __syncthreads();
-    TRP(1);
     if (tid < nk && sDst[tid] < 64) sPk[sDst[tid]] = tid;
     // words of the block live in (Ab, sb), the others in (A, stride)
     auto wp = [&](int row, int w) -> uint64_t * {
@@ -128,7 +115,6 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
         if (w < nwords && w != wc) stage[e] = *wp(R + sSrc[k], w);
     }
     __syncthreads();
-    TRP(2);
     for (int e = tid; e < nk * SWAP_W; e += POST_THREADS) {
         const int k = e / SWAP_W, w = w0 + e % SWAP_W;
         if (w < nwords && w != wc) *wp(R + sDst[k], w) = stage[e];
@@ -145,7 +131,6 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
                 k >= 0 ? stage[k * SWAP_W + (w - w0)] : *wp(R + t, w);
         }
     }
-    TRP(3);
 }
 
 hipError_t launch_leaf(uint64_t *A, int64_t stride, uint64_t *Ab, int64_t sb, int blk_lo,

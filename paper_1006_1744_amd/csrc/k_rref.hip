@@ -35,9 +35,14 @@ __device__ inline uint64_t pdep64(uint64_t x, uint64_t mask) {
     return out;
 }
 
+// A rank outside [0, rmax] (not a gf2_pls result) is clamped into it.
+__device__ inline int clamp_rank(const int32_t *rank, int rmax) {
+    return min(max(*rank, 0), rmax);
+}
+
 // Pivot mask from Q[0..r): set bit Q[t].  PM must be zero on entry.
-__global__ void pivot_mask_kernel(uint64_t *PM, const int32_t *Q, const int32_t *rank) {
-    const int r = *rank;
+__global__ void pivot_mask_kernel(uint64_t *PM, const int32_t *Q, const int32_t *rank, int rmax) {
+    const int r = clamp_rank(rank, rmax);
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < r; t += gridDim.x * blockDim.x) {
         int q = Q[t];
         atomicOr((unsigned long long *)&PM[q >> 6], 1ull << (q & 63));
@@ -45,11 +50,20 @@ __global__ void pivot_mask_kernel(uint64_t *PM, const int32_t *Q, const int32_t 
 }
 
 // NM = ~PM inside [0, n); exclusive prefix sums of popcounts (one block).
+// Also the solve's extents rr = {0, r, ceil((n - r) / 64)}.
 __global__ __launch_bounds__(1024) void mask_prefix_kernel(const uint64_t *PM, uint64_t *NM,
-                                                           int32_t *prefP, int32_t *prefN, int n) {
+                                                           int32_t *prefP, int32_t *prefN, int n,
+                                                           const int32_t *rank, int rmax,
+                                                           int32_t *rr) {
     __shared__ int32_t sp[1024], sn[1024];
     const int nw = (n + 63) / 64;
     const int tid = threadIdx.x;
+    if (tid == 0) {
+        const int r = clamp_rank(rank, rmax);
+        rr[0] = 0;
+        rr[1] = r;
+        rr[2] = (n - r + 63) / 64;
+    }
     const int per = (nw + 1023) / 1024;
     const int w0 = tid * per, w1 = min(nw, w0 + per);
     int cp = 0, cn = 0;
@@ -95,10 +109,12 @@ __device__ inline void or_bits(uint64_t *row, int off, int cnt, uint64_t v) {
 // it) compressed by PM into Uc and by NM into Xc.  Uc, Xc zero on entry.  One
 // thread per (row, word), the word index fastest, so neighbouring threads read
 // neighbouring words of a row and OR into neighbouring words of its compact rows.
-__global__ void rref_gather_kernel(const uint64_t *Ap, int64_t sap, const int32_t *Q, int r, int nw,
+__global__ void rref_gather_kernel(const uint64_t *Ap, int64_t sap, const int32_t *Q, int nw,
                                    const uint64_t *PM, const uint64_t *NM, const int32_t *prefP,
                                    const int32_t *prefN, uint64_t *Uc, int64_t su, uint64_t *Xc,
-                                   int64_t sx) {
+                                   int64_t sx, const int32_t *rr) {
+    if (rr[2] == 0) return;   // no non-pivot column: nothing to solve
+    const int r = rr[1];
     const int64_t total = (int64_t)r * nw;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -121,9 +137,10 @@ __global__ void rref_gather_kernel(const uint64_t *Ap, int64_t sap, const int32_
 
 // R row i: pivot one at Q[i] (i < r) and the solved non-pivot bits spread back
 // by NM; rows >= r are zero.  One thread per (row, word), the word index fastest.
-__global__ void rref_scatter_kernel(uint64_t *R, int64_t sr, int m, const int32_t *Q, int r,
-                                    const uint64_t *NM, const int32_t *prefN, const uint64_t *Xc,
-                                    int64_t sx, int nw) {
+__global__ void rref_scatter_kernel(uint64_t *R, int64_t sr, int m, const int32_t *Q,
+                                    const int32_t *rr, const uint64_t *NM, const int32_t *prefN,
+                                    const uint64_t *Xc, int64_t sx, int nw) {
+    const int r = rr[1];
     const int64_t total = (int64_t)m * nw;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -146,6 +163,32 @@ __global__ void rref_scatter_kernel(uint64_t *R, int64_t sr, int m, const int32_
     }
 }
 
+// Uc rows [0, r) x ceil(r / 64) words and Xc rows [0, r) x rr[2] words <- 0
+// (nothing when there is no non-pivot column).
+__global__ void rref_zero_kernel(uint64_t *Uc, int64_t su, uint64_t *Xc, int64_t sx,
+                                 const int32_t *rr) {
+    const int r = rr[1], nx = rr[2], nu = (r + 63) / 64;
+    if (nx == 0) return;
+    const int64_t tu = (int64_t)r * nu, total = tu + (int64_t)r * nx;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        if (e < tu)
+            Uc[(e / nu) * su + (e % nu)] = 0ull;
+        else
+            Xc[((e - tu) / nx) * sx + ((e - tu) % nx)] = 0ull;
+    }
+}
+
+hipError_t launch_rref_zero(uint64_t *Uc, int64_t su, uint64_t *Xc, int64_t sx, int rmax,
+                            const int32_t *rr, hipStream_t st) {
+    if (rmax <= 0) return hipSuccess;
+    int64_t blocks = ((int64_t)rmax * (su + sx) + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(rref_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, Uc, su, Xc, sx,
+                       rr);
+    return hipGetLastError();
+}
+
 __global__ void zero_rows_kernel(uint64_t *X, int64_t sx, int rows, int words) {
     int64_t total = (int64_t)rows * words;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -164,7 +207,7 @@ hipError_t launch_zero_rows(uint64_t *X, int64_t sx, int rows, int words, hipStr
 }
 
 hipError_t launch_rref_masks(uint64_t *PM, uint64_t *NM, int32_t *prefP, int32_t *prefN,
-                             const int32_t *Q, const int32_t *rank, int n, int rmax,
+                             const int32_t *Q, const int32_t *rank, int n, int rmax, int32_t *rr,
                              hipStream_t st) {
     const int nw = (n + 63) / 64;
     hipError_t e = launch_zero_rows(PM, nw, 1, nw, st);
@@ -172,33 +215,34 @@ hipError_t launch_rref_masks(uint64_t *PM, uint64_t *NM, int32_t *prefP, int32_t
     int blocks = (rmax + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(pivot_mask_kernel, dim3(blocks), dim3(256), 0, st, PM, Q, rank);
+    hipLaunchKernelGGL(pivot_mask_kernel, dim3(blocks), dim3(256), 0, st, PM, Q, rank, rmax);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(mask_prefix_kernel, dim3(1), dim3(1024), 0, st, PM, NM, prefP, prefN, n);
+    hipLaunchKernelGGL(mask_prefix_kernel, dim3(1), dim3(1024), 0, st, PM, NM, prefP, prefN, n, rank,
+                       rmax, rr);
     return hipGetLastError();
 }
 
-hipError_t launch_rref_gather(const uint64_t *Ap, int64_t sap, const int32_t *Q, int r, int n,
+hipError_t launch_rref_gather(const uint64_t *Ap, int64_t sap, const int32_t *Q, int rmax, int n,
                               const uint64_t *PM, const uint64_t *NM, const int32_t *prefP,
                               const int32_t *prefN, uint64_t *Uc, int64_t su, uint64_t *Xc,
-                              int64_t sx, hipStream_t st) {
-    if (r <= 0) return hipSuccess;
+                              int64_t sx, const int32_t *rr, hipStream_t st) {
+    if (rmax <= 0) return hipSuccess;
     const int nw = (n + 63) / 64;
-    int64_t blocks = ((int64_t)r * nw + 255) / 256;
+    int64_t blocks = ((int64_t)rmax * nw + 255) / 256;
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(rref_gather_kernel, dim3((unsigned)blocks), dim3(256), 0, st, Ap, sap, Q, r,
-                       nw, PM, NM, prefP, prefN, Uc, su, Xc, sx);
+    hipLaunchKernelGGL(rref_gather_kernel, dim3((unsigned)blocks), dim3(256), 0, st, Ap, sap, Q, nw,
+                       PM, NM, prefP, prefN, Uc, su, Xc, sx, rr);
     return hipGetLastError();
 }
 
-hipError_t launch_rref_scatter(uint64_t *R, int64_t sr, int m, int n, const int32_t *Q, int r,
-                               const uint64_t *NM, const int32_t *prefN, const uint64_t *Xc,
-                               int64_t sx, hipStream_t st) {
+hipError_t launch_rref_scatter(uint64_t *R, int64_t sr, int m, int n, const int32_t *Q,
+                               const int32_t *rr, const uint64_t *NM, const int32_t *prefN,
+                               const uint64_t *Xc, int64_t sx, hipStream_t st) {
     const int nw = (n + 63) / 64;
     if (m <= 0 || nw <= 0) return hipSuccess;
     int64_t blocks = ((int64_t)m * nw + 255) / 256;
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(rref_scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, st, R, sr, m, Q, r,
+    hipLaunchKernelGGL(rref_scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, st, R, sr, m, Q, rr,
                        NM, prefN, Xc, sx, nw);
     return hipGetLastError();
 }

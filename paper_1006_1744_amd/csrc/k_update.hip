@@ -1,14 +1,11 @@
 // Table-driven updates of the MMPF base case and the small pieces of the
 // recursive driver.
 //
-// trsm_base_kernel   X <- L^{-1} X for a block of at most 64 rows (unit lower
-//                    triangular L = the block's own bits below the diagonal in
-//                    one word column), or X <- U^{-1} X with the bits above it.
-//                    Rows are processed in groups of k: within a group by plain
-//                    substitution, then the group's 2^k combinations are
-//                    tabulated in LDS (MakeTable, Section 3.1) and every later
-//                    row of the block adds one table row per group
-//                    (AddRowsFromTable, Appendix A).
+// trsm_block_kernel  X <- T^{-1} X for up to 16 blocks of 64 rows (unit lower or
+//                    unit upper T): 64 x 64 inverses of the diagonal blocks, then
+//                    block substitution with tables of 16 combinations of 4 rows
+//                    (MakeTable with k = 4, Section 3.1; AddRowsFromTable,
+//                    Appendix A).
 // table_update_kernel Schur update after one panel: every row below the
 //                    panel's pivot rows adds L[i] * U on the target columns, with
 //                    L[i] the row's (final, compressed) panel word and U the
@@ -79,64 +76,6 @@ hipError_t launch_copy_rows(uint64_t *dst, int64_t sd, int dw0, const uint64_t *
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ TRSM
-// X <- T^{-1} X on at most 64 rows: T^{-1} is formed by one wave (column-wise
-// substitution, tri_inverse64), then every output row is a combination of the
-// block's rows: X[i] = sum_j Tinv[i][j] B[j], evaluated with tables of all 16
-// combinations of each 4 consecutive rows (MakeTable with k = 4, Section 3.1)
-// and one table row per group (AddRowsFromTable).
-constexpr int TRSM_THREADS = 256;
-constexpr int TRSM_TW = 16;   // tile words
-constexpr int TRSM_K = 4;
-constexpr int TRSM_NG = 64 / TRSM_K;
-
-__global__ __launch_bounds__(TRSM_THREADS) void trsm_base_kernel(
-    uint64_t *A, int64_t stride, const uint64_t *Lm, int64_t sl, int m, RowRange rows, int lw,
-    int w_lo, int w_hi, const int32_t *rk, int lower) {
-    __shared__ uint64_t sB[64 * TRSM_TW];
-    __shared__ uint64_t sT[TRSM_NG * (1 << TRSM_K) * TRSM_TW];
-    __shared__ uint64_t sL[64];
-    __shared__ uint64_t sInv[64];
-    int r0, r1;
-    eval_range(rk, m, rows, r0, r1);
-    const int nr = min(r1 - r0, 64);
-    if (nr <= 1) return;
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int w0 = w_lo + blockIdx.x * TRSM_TW;
-    const int tw_n = min(TRSM_TW, w_hi - w0);
-    if (tw_n <= 0) return;
-    for (int e = tid; e < 64 * TRSM_TW; e += TRSM_THREADS) {
-        int s = e / TRSM_TW, w = e % TRSM_TW;
-        sB[e] = (s < nr && w < tw_n) ? A[(int64_t)(r0 + s) * stride + w0 + w] : 0ull;
-    }
-    if (tid < 64) {
-        const uint64_t keep = nr == 64 ? ~0ull : ((1ull << nr) - 1);
-        sL[tid] = tid < nr ? (Lm[(int64_t)(r0 + tid) * sl + lw] & keep) : 0ull;
-    }
-    __syncthreads();
-    if (tid < 64) sInv[lane] = tri_inverse64(sL, lane, lower != 0);
-    build_tables_k4<TRSM_TW>(sB, nr, TRSM_NG, sT, tid, TRSM_THREADS);
-    for (int e = tid; e < nr * TRSM_TW; e += TRSM_THREADS) {
-        const int i = e / TRSM_TW, w = e % TRSM_TW;
-        const uint64_t c = sInv[i];
-        uint64_t x = 0;
-#pragma unroll
-        for (int g = 0; g < TRSM_NG; g++)
-            x ^= sT[((g << TRSM_K) + (int)((c >> (TRSM_K * g)) & ((1u << TRSM_K) - 1))) * TRSM_TW + w];
-        if (w < tw_n) A[(int64_t)(r0 + i) * stride + w0 + w] = x;
-    }
-}
-
-hipError_t launch_trsm_base(uint64_t *A, int64_t stride, const uint64_t *Lm, int64_t sl, int m,
-                            RowRange rows, int lw, int w_lo, int w_hi, const int32_t *rk,
-                            int lower, hipStream_t st) {
-    if (w_hi <= w_lo) return hipSuccess;
-    int nb = (w_hi - w_lo + TRSM_TW - 1) / TRSM_TW;
-    hipLaunchKernelGGL(trsm_base_kernel, dim3(nb), dim3(TRSM_THREADS), 0, st, A, stride, Lm, sl, m,
-                       rows, lw, w_lo, w_hi, rk, lower);
-    return hipGetLastError();
-}
-
 // ------------------------------------------------------- blocked TRSM
 // X <- T^{-1} X for up to TB_NB blocks of 64 rows in one launch (unit lower or
 // unit upper T, its rows in Lm), one thread per row, two words of X per block.
@@ -162,7 +101,7 @@ template <int TW>
 __global__ __launch_bounds__(TB_THREADS) void trsm_block_kernel(
     uint64_t *A, int64_t stride, const uint64_t *Lm, int64_t sl, int m, RowRange rows, int lw0,
     int w_lo, int w_hi, const int32_t *rk, int lower, int nbmax, const uint64_t *linv_store,
-    uint64_t *Bt, int64_t sbt, int kw0) {
+    uint64_t *Bt, int64_t sbt, int kw0, const int32_t *nwd) {
     __shared__ __attribute__((aligned(16))) uint64_t sX[TB_NB * 64 * TW];
     __shared__ __attribute__((aligned(16))) uint64_t sT[256 * TW];
     __shared__ uint64_t sInv[TB_NB * 64];
@@ -174,6 +113,7 @@ __global__ __launch_bounds__(TB_THREADS) void trsm_block_kernel(
     if (nr <= 1 && Bt == nullptr) return;
     const int nb = max(nr + 63, 0) / 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (nwd) w_hi = min(w_hi, w_lo + *nwd);
     const int w0 = w_lo + blockIdx.x * TW;
     const int tw_n = min(TW, w_hi - w0);
     if (tw_n <= 0) return;
@@ -281,17 +221,17 @@ int trsm_block_max_rows() { return TB_NB * 64; }
 hipError_t launch_trsm_block(uint64_t *A, int64_t stride, const uint64_t *Lm, int64_t sl, int m,
                              RowRange rows, int lw0, int w_lo, int w_hi, const int32_t *rk,
                              int lower, int nbmax, const uint64_t *linv_store, uint64_t *Bt,
-                             int64_t sbt, int kw0, hipStream_t st) {
+                             int64_t sbt, int kw0, hipStream_t st, const int32_t *nwd) {
     if (w_hi <= w_lo) return hipSuccess;
     if (nbmax > TB_NB) nbmax = TB_NB;
     const int words = w_hi - w_lo;
     if (words >= 512) {   // at least 256 blocks of word pairs
         hipLaunchKernelGGL((trsm_block_kernel<2>), dim3((words + 1) / 2), dim3(TB_THREADS), 0, st, A,
                            stride, Lm, sl, m, rows, lw0, w_lo, w_hi, rk, lower, nbmax, linv_store,
-                           Bt, sbt, kw0);
+                           Bt, sbt, kw0, nwd);
     } else {
         hipLaunchKernelGGL((trsm_block_kernel<1>), dim3(words), dim3(TB_THREADS), 0, st, A, stride, Lm,
-                           sl, m, rows, lw0, w_lo, w_hi, rk, lower, nbmax, linv_store, Bt, sbt, kw0);
+                           sl, m, rows, lw0, w_lo, w_hi, rk, lower, nbmax, linv_store, Bt, sbt, kw0, nwd);
     }
     return hipGetLastError();
 }
@@ -332,13 +272,6 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
     uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk, int b, int w_lo, int w_hi,
     int k, int tables, int TW, int lg_tpr, const uint64_t *linv, const uint64_t *Bbuf,
     int64_t bstride) {
-#ifdef GF2_TRACE
-    uint64_t *trace_upd = reinterpret_cast<uint64_t *>(const_cast<char *>(reinterpret_cast<const char *>(linv)) + 64 * 8 + 4 * 257 + 4 + 24 * 8 + 8 * 8);
-#define TRU(i) do { if (threadIdx.x == 0 && blockIdx.x == 0 && blockIdx.y == 0 && b == 0) trace_upd[i] = __builtin_amdgcn_s_memrealtime(); } while (0)
-#else
-#define TRU(i) do {} while (0)
-#endif
-    TRU(0);
     extern __shared__ uint64_t tu_lds[];
     uint64_t *sLT = tu_lds;                 // [8][256]   combinations of L^{-1} rows
     uint64_t *sInv = sLT + 8 * 256;         // [64]
@@ -387,9 +320,7 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
             if (w < wn) x[w] = px[w];
     }
     block_sync<true>();
-    TRU(1);
     build_tables_8x8<TU_THREADS, true>(sInv, sLT, tid);
-    TRU(2);
     const int ng = (r + k - 1) / k;
     const int npass = (ng + tables - 1) / tables;
     const int esz = 1 << k;
@@ -409,18 +340,12 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
             }
         }
         uint64_t c = 0;
-#ifdef GF2_TRACE
-        if (act && c == 0x123456789ull) x[0] ^= 1;   // keep the loads before the stamp
-        __syncthreads();
-#endif
-        TRU(6);
         for (int pass = 0; pass < npass; pass++) {
             const int g0 = pass * tables, g1 = min(ng, g0 + tables);
             if (chunk == 0 || npass > 1) {
                 if (chunk > 0 || pass > 0) block_sync<true>();
                 build_group_tables<true>(sB + (size_t)g0 * k * TW, r - g0 * k, k, g1 - g0, sT, TW,
                                          tid, TU_THREADS);
-                TRU(3);
                 if (pivots_here && chunk == 0 && pq < pstep) {
                     for (int t = pq; t < r; t += pstep) {
                         const uint64_t ct = sInv[t];
@@ -456,10 +381,8 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
                 if (w < wn) px[w] = x[w];
         }
     }
-    TRU(4);
     if (pivots_here && pq < pstep && wq < tw_n)
         for (int t = pq; t < r; t += pstep) A[(int64_t)(R + t) * stride + w0 + wq] = sU[t * TW + wq];
-    TRU(5);
 }
 
 hipError_t launch_table_update(uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk,

@@ -66,7 +66,7 @@ def test_null_context_rejected(lib):
     import paper_1006_1744_amd as g
     m = g.Mat(None, 10, 10, 1)
     assert lib.gf2_pls(None, m, None, None, None, None, None, 0, None) == -1
-    assert lib.gf2_rref(None, m, None, None, m, None, 0, None) == -1
+    assert lib.gf2_rref(None, m, None, None, m, None, None, 0, None) == -1
     assert lib.gf2_addmul(None, m, m, m, 0, None, 0, None) == -1
 
 

@@ -3,8 +3,10 @@ times (one gf2_pls call with the default schedule, then gf2_rref), against the
 CPU oracle run on the same input: rank, P, Q and every word of the in-place
 result bit for bit.  The RREF is checked through properties that pin it at any
 size (rows past the rank are zero, the pivot columns form the identity, and
-S = U_Q R by Freivalds' test with random vectors), because forming it on the
-host by Gauss-Jordan at these sizes would take minutes."""
+S = U_Q R by Freivalds' test with 64 random vectors per identity, so a wrong R
+passes with probability at most 2^-64), because forming it on the host by
+Gauss-Jordan at these sizes would take minutes; element-wise RREF parity at
+sizes that reach the same product tiles is in test_gpu_rref.py."""
 from __future__ import annotations
 
 import sys
@@ -14,6 +16,7 @@ import pytest
 
 import oracle
 import synth
+from rref_checks import check_rref_properties, s_rows
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -29,63 +32,10 @@ def say(msg):
     sys.stdout.flush()
 
 
-def matvec(M: np.ndarray, v: np.ndarray, rows: int, chunk: int = 4096) -> np.ndarray:
-    """Parity of popcount(M[i] & v) for i < rows (packed rows and vector)."""
-    out = np.empty(rows, dtype=np.uint8)
-    for a in range(0, rows, chunk):
-        b = min(rows, a + chunk)
-        out[a:b] = np.bitwise_count(M[a:b] & v[None, :]).sum(axis=1, dtype=np.int64) & 1
-    return out
-
-
-def scatter_bits(y: np.ndarray, Q: np.ndarray, n: int) -> np.ndarray:
-    """Packed n-bit vector with bit Q[j] = y[j]."""
-    z = np.zeros((n + 63) // 64, dtype=np.uint64)
-    on = Q[y.astype(bool)].astype(np.int64)
-    np.bitwise_or.at(z, on // 64, np.left_shift(np.uint64(1), (on % 64).astype(np.uint64)))
-    return z
-
-
-def s_rows(Ap: np.ndarray, r: int, Q: np.ndarray, n: int) -> np.ndarray:
-    """S (r x n, packed) from the in-place result: stored bits right of Q[i], one at Q[i]."""
-    W = (n + 63) // 64
-    S = np.ascontiguousarray(Ap[:r, :W]).copy()
-    q = Q[:r].astype(np.int64)
-    cols = np.arange(W, dtype=np.int64)[None, :]
-    w = (q // 64)[:, None]
-    S[cols < w] = 0
-    lo = (q % 64).astype(np.uint64)
-    # bits at or below the pivot in its word are cleared (all of them when lo == 63)
-    low = np.where(lo == 63, ~np.uint64(0),
-                   np.left_shift(np.uint64(1), np.minimum(lo + np.uint64(1), np.uint64(63))) - np.uint64(1))
-    keep = ~low
-    idx = np.arange(r)
-    S[idx, q // 64] = (S[idx, q // 64] & keep) | np.left_shift(np.uint64(1), lo)
-    return S
-
-
-def check_rref_properties(R: np.ndarray, S: np.ndarray, r: int, Q: np.ndarray, n: int,
-                          trials: int = 16):
-    W = (n + 63) // 64
-    assert not R[r:, :W].any(), "rows past the rank must be zero"
-    rng = np.random.default_rng(99)
-    for _ in range(trials):
-        # R[:, Q] = I:  R z(y) = y for a random r-vector y
-        y = rng.integers(0, 2, r, dtype=np.uint8)
-        assert np.array_equal(matvec(R, scatter_bits(y, Q[:r], n), r), y), "R[:, Q] != I"
-        # S = U_Q R with U_Q = S[:, Q]:  S v = S z(R v)
-        v = rng.integers(0, np.iinfo(np.uint64).max, W, dtype=np.uint64, endpoint=True)
-        if n % 64:
-            v[-1] &= np.uint64((1 << (n % 64)) - 1)
-        Rv = matvec(R, v, r)
-        assert np.array_equal(matvec(S, v, r), matvec(S, scatter_bits(Rv, Q[:r], n), r)), \
-            "S != U_Q R"
-
-
 def run_full(A, m, n, s=None, rref=True):
     dA = g.to_device(A)
     P, Q, rank = g.pls(dA, m, n, s)
-    R = g.rref(dA, m, n, Q, rank) if rref else None
+    R = g.rref(dA, m, n, Q, rank, s=s) if rref else None
     torch.cuda.synchronize()
     return (int(rank.item()), P.cpu().numpy(), Q.cpu().numpy(), g.to_host(dA),
             g.to_host(R) if rref else None)
@@ -125,7 +75,7 @@ def test_full_65536_dense_all_schur_variants():
     compare("65536 XOR", got_x, want)
 
 
-def test_full_65536_sparse():
+def test_full_65536_sparse_all_schur_variants():
     m = n = 65536
     A = synth.random_bernoulli(m, n, 0.01, 2)
     say("[full] 65536^2 p=0.01 seed 2")
@@ -134,9 +84,50 @@ def test_full_65536_sparse():
     compare("65536 sparse", got, want)
     r, P, Q, Ap = want
     check_rref_properties(got[4], s_rows(Ap, r, Q, n), r, Q, n)
+    del got
+    for name, v in (("int8 MFMA", g.SCHUR_MFMA), ("XOR", g.SCHUR_XOR)):
+        say(f"[full] 65536^2 p=0.01 with the {name} Schur product")
+        got_v = run_full(A, m, n, g.Sched(8, 8, 512, v), rref=False)
+        compare(f"65536 sparse {name}", got_v, want)
+        del got_v
 
 
-def test_full_32768x131072():
+def test_full_65536_dense_seed2():
+    m = n = 65536
+    A = synth.random_half(m, n, 2)
+    say("[full] 65536^2 p=1/2 seed 2")
+    got = run_full(A, m, n)
+    compare("65536 seed 2", got, oracle.pls(A, m, n))
+
+
+def test_full_32768_iid_mmpf_and_recursive():
+    m = n = 32768
+    A = synth.random_half(m, n, 1)
+    say("[full] 32768^2 p=1/2 seed 1, recursive")
+    want = oracle.pls(A, m, n)
+    got = run_full(A, m, n)
+    compare("32768 iid, recursive", got, want)
+    r, P, Q, Ap = want
+    if r < n:
+        check_rref_properties(got[4], s_rows(Ap, r, Q, n), r, Q, n)
+    del got
+    say("[full] the same matrix by MMPF alone")
+    got_m = run_full(A, m, n, g.Sched(8, 8, 1 << 20, g.SCHUR_FP4), rref=False)
+    compare("32768 iid, MMPF", got_m, want)
+
+
+def test_full_32768x131072_sparse():
+    m, n = 32768, 131072
+    A = synth.random_bernoulli(m, n, 0.01, 4)
+    say("[full] 32768x131072 p=0.01 seed 4")
+    got = run_full(A, m, n)
+    want = oracle.pls(A, m, n)
+    compare("32768x131072 sparse", got, want)
+    r, P, Q, Ap = want
+    check_rref_properties(got[4], s_rows(Ap, r, Q, n), r, Q, n)
+
+
+def test_full_32768x131072_all_schur_variants():
     m, n = 32768, 131072
     A = synth.random_half(m, n, 3)
     say("[full] 32768x131072 p=1/2 seed 3")
@@ -144,7 +135,15 @@ def test_full_32768x131072():
     want = oracle.pls(A, m, n)
     compare("32768x131072", got, want)
     r, P, Q, Ap = want
-    check_rref_properties(got[4], s_rows(Ap, r, Q, n), r, Q, n)
+    S = s_rows(Ap, r, Q, n)
+    check_rref_properties(got[4], S, r, Q, n)
+    del got
+    for name, v in (("int8 MFMA", g.SCHUR_MFMA), ("XOR", g.SCHUR_XOR)):
+        say(f"[full] 32768x131072 with the {name} Schur product (PLS and RREF)")
+        got_v = run_full(A, m, n, g.Sched(8, 8, 512, v))
+        compare(f"32768x131072 {name}", got_v, want)
+        check_rref_properties(got_v[4], S, r, Q, n)
+        del got_v
 
 
 def test_full_32768_planted_rank_mmpf_and_recursive():
