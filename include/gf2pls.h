@@ -107,6 +107,24 @@ int gf2_pls(gf2_ctx *ctx, gf2_mat A, int32_t *P, int32_t *Q, int32_t *rank,
             const gf2_sched *s, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * gf2_pls without a workspace argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, result and asynchrony as gf2_pls; the
+ * scratch space is a fixed array of GF2_NOALLOC_SCRATCH_BYTES bytes that the
+ * library holds on each device it runs on until the process ends.  Problems
+ * whose gf2_pls_workspace_bytes exceeds that size return GF2_E_UNSUPPORTED
+ * (nothing enqueued; 16 MiB covers 16384 x 16384 under the default schedule).
+ * No HIP allocation is made by this call.  Every call on one device shares that
+ * device's array: calls that overlap in time on one device (two streams, or two
+ * host threads) race and give undefined results; calls ordered on one stream are
+ * safe.  Everything the call needs zeroed is cleared by its own kernels.
+ */
+#define GF2_NOALLOC_SCRATCH_BYTES (16u << 20)
+int gf2_pls_noalloc(gf2_ctx *ctx, gf2_mat A, int32_t *P, int32_t *Q, int32_t *rank,
+                    const gf2_sched *s, void *stream);
+size_t gf2_pls_noalloc_max_bytes(void);
+
+/*
  * Explicit factors from a gf2_pls result (Section 2's A = P L S; in-place layout
  * of Sections 4-5).  A_pls, Q, rank are gf2_pls outputs (device); A_pls is only
  * read.  With rmax = min(m, n):

@@ -17,7 +17,7 @@ import torch
 
 from .build import LIB as _LIB_PATH
 
-__all__ = ["Sched", "Mat", "get_lib", "default_sched", "pls", "rref", "addmul", "to_device",
+__all__ = ["Sched", "Mat", "get_lib", "default_sched", "pls", "pls_noalloc", "rref", "addmul", "to_device",
            "to_host", "workspace", "Batch", "SCHUR_XOR", "SCHUR_MFMA", "SCHUR_FP4", "GF2Error"]
 
 SCHUR_XOR = 0
@@ -83,6 +83,10 @@ def _load():
     L.gf2_pls_workspace_bytes.restype = sz
     L.gf2_pls.argtypes = [vp, Mat, vp, vp, vp, ctypes.POINTER(Sched), vp, sz, vp]
     L.gf2_pls.restype = i32
+    L.gf2_pls_noalloc.argtypes = [vp, Mat, vp, vp, vp, ctypes.POINTER(Sched), vp]
+    L.gf2_pls_noalloc.restype = i32
+    L.gf2_pls_noalloc_max_bytes.argtypes = []
+    L.gf2_pls_noalloc_max_bytes.restype = sz
     L.gf2_pls_unpack.argtypes = [vp, Mat, vp, vp, Mat, Mat, vp]
     L.gf2_pls_unpack.restype = i32
     L.gf2_rref_workspace_bytes.argtypes = [i64, i64]
@@ -225,6 +229,22 @@ def pls(A: torch.Tensor, m: int, n: int, s: Sched | None = None, ws: torch.Tenso
     _check(get_lib().gf2_pls(ctx(dev.index), _mat(A, m, n), P.data_ptr(), Q.data_ptr(), rank.data_ptr(),
                        ctypes.byref(s) if s is not None else None, ws.data_ptr(), ws.numel(),
                        _stream(stream)))
+    return P[:m], Q[:n], rank
+
+
+def pls_noalloc(A: torch.Tensor, m: int, n: int, s: Sched | None = None,
+                P: torch.Tensor | None = None, Q: torch.Tensor | None = None,
+                rank: torch.Tensor | None = None, stream=None):
+    """gf2_pls_noalloc: in-place PLS of A using the library's fixed per-device
+    scratch instead of a workspace.  P, Q and rank must be passed in by callers
+    that cannot allocate; returns (P, Q, rank)."""
+    dev = A.device
+    P = torch.empty(max(m, 1), dtype=torch.int32, device=dev) if P is None else P
+    Q = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if Q is None else Q
+    rank = torch.empty(1, dtype=torch.int32, device=dev) if rank is None else rank
+    _check(get_lib().gf2_pls_noalloc(ctx(dev.index), _mat(A, m, n), P.data_ptr(), Q.data_ptr(),
+                                     rank.data_ptr(), ctypes.byref(s) if s is not None else None,
+                                     _stream(stream)))
     return P[:m], Q[:n], rank
 
 

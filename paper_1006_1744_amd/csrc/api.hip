@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/gf2pls.h"
@@ -39,7 +40,34 @@ struct gf2_ctx {
     int64_t plog_cap = 0;
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
+    void *scratch = nullptr;   // this device's copy of `scratch` (device address)
 };
+
+// Scratch memory of gf2_pls_noalloc: one copy per device, held until the process
+// ends.  Its name is a host-side stand-in; kernels only ever receive the device
+// address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[GF2_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (current), looked up once per device.
+hipError_t scratch_address(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+}  // namespace
 
 namespace gf2 {
 int table_update_tile_words(int k, int tables);
@@ -323,6 +351,41 @@ int check_mat(const gf2_mat &A) {
     return GF2_OK;
 }
 
+// Launches the recursion for A with its workspace at `base` (layout L).
+int pls_run(gf2_ctx *ctx, const gf2_mat &A, int32_t *P, int32_t *Q, int32_t *rank,
+            const gf2_sched &ss, const PlsLayout &L, char *base, hipStream_t st) {
+    if (hipSetDevice(ctx->device) != hipSuccess) return GF2_E_HIP;
+    PlsDriver d;
+    d.dry = false;
+    d.ctx = ctx;
+    d.A = A.words;
+    d.stride = A.stride;
+    d.m = (int)A.m;
+    d.n = (int)A.n;
+    d.nb = (int)((A.n + 63) / 64);
+    d.s = ss;
+    d.rk = (int32_t *)(base + L.rk_off);
+    d.info = (int32_t *)(base + L.info_off);
+    d.Bt = (uint64_t *)(base + L.bt_off);
+    d.bt_words = L.bt_words;
+    d.Bt2 = (uint64_t *)(base + L.bt2_off);
+    d.bt2_words = L.bt2_words;
+    d.Bbuf = (uint64_t *)(base + L.bb_off);
+    d.bstride = L.bstride;
+    d.linv = (const uint64_t *)(base + L.info_off + panel_info_linv_offset());
+    d.linv_store = (uint64_t *)(base + L.linv_off);
+    d.pbuf = (uint64_t *)(base + L.pbuf_off);
+    d.pbuf_w = L.pbuf_w;
+    d.cus = ctx->cus;
+    d.P = P;
+    d.Q = Q;
+    d.st = st;
+    if (A.m > 0 && A.n > 0) d.run();
+    else d.chk(launch_fill_i32(d.rk, 0, d.nb + 1, st));
+    d.chk(launch_finalize(P, Q, rank, d.rk, d.nb, d.m, d.n, st));
+    return d.err == hipSuccess ? GF2_OK : GF2_E_HIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -340,6 +403,10 @@ int gf2_ctx_create(gf2_ctx **out, int device) {
     c->device = device;
     c->cus = prop.multiProcessorCount;
     c->batch_bpc = batch_blocks_per_cu();
+    if (scratch_address(device, &c->scratch) != hipSuccess) {
+        delete c;
+        return GF2_E_HIP;
+    }
     if (mlp_prepare() != hipSuccess) {
         delete c;
         return GF2_E_HIP;
@@ -449,39 +516,24 @@ int gf2_pls(gf2_ctx *ctx, gf2_mat A, int32_t *P, int32_t *Q, int32_t *rank, cons
     PlsLayout L = pls_layout(A.m, A.n, ss);
     if (!ws || ws_bytes < L.total) return GF2_E_WORKSPACE;
     if (((uintptr_t)ws & 255) != 0) return GF2_E_ALIGN;
-    hipStream_t st = (hipStream_t)stream;
-    if (hipSetDevice(ctx->device) != hipSuccess) return GF2_E_HIP;
-    char *base = (char *)ws;
-    PlsDriver d;
-    d.dry = false;
-    d.ctx = ctx;
-    d.A = A.words;
-    d.stride = A.stride;
-    d.m = (int)A.m;
-    d.n = (int)A.n;
-    d.nb = (int)((A.n + 63) / 64);
-    d.s = ss;
-    d.rk = (int32_t *)(base + L.rk_off);
-    d.info = (int32_t *)(base + L.info_off);
-    d.Bt = (uint64_t *)(base + L.bt_off);
-    d.bt_words = L.bt_words;
-    d.Bt2 = (uint64_t *)(base + L.bt2_off);
-    d.bt2_words = L.bt2_words;
-    d.Bbuf = (uint64_t *)(base + L.bb_off);
-    d.bstride = L.bstride;
-    d.linv = (const uint64_t *)(base + L.info_off + panel_info_linv_offset());
-    d.linv_store = (uint64_t *)(base + L.linv_off);
-    d.pbuf = (uint64_t *)(base + L.pbuf_off);
-    d.pbuf_w = L.pbuf_w;
-    d.cus = ctx->cus;
-    d.P = P;
-    d.Q = Q;
-    d.st = st;
-    if (A.m > 0 && A.n > 0) d.run();
-    else d.chk(launch_fill_i32(d.rk, 0, d.nb + 1, st));
-    d.chk(launch_finalize(P, Q, rank, d.rk, d.nb, d.m, d.n, st));
-    return d.err == hipSuccess ? GF2_OK : GF2_E_HIP;
+    return pls_run(ctx, A, P, Q, rank, ss, L, (char *)ws, (hipStream_t)stream);
 }
+
+int gf2_pls_noalloc(gf2_ctx *ctx, gf2_mat A, int32_t *P, int32_t *Q, int32_t *rank,
+                    const gf2_sched *s, void *stream) {
+    if (!ctx) return GF2_E_ARG;
+    int rc = check_mat(A);
+    if (rc != GF2_OK) return rc;
+    gf2_sched ss = s ? *s : default_sched();
+    if (!sched_ok(&ss)) return GF2_E_ARG;
+    if (!rank || (A.m > 0 && !P) || (A.n > 0 && !Q)) return GF2_E_ARG;
+    PlsLayout L = pls_layout(A.m, A.n, ss);
+    if (L.total > (size_t)GF2_NOALLOC_SCRATCH_BYTES) return GF2_E_UNSUPPORTED;
+    if (!ctx->scratch) return GF2_E_HIP;
+    return pls_run(ctx, A, P, Q, rank, ss, L, (char *)ctx->scratch, (hipStream_t)stream);
+}
+
+size_t gf2_pls_noalloc_max_bytes(void) { return (size_t)GF2_NOALLOC_SCRATCH_BYTES; }
 
 int gf2_pls_unpack(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int32_t *rank,
                    gf2_mat L_out, gf2_mat S_out, void *stream) {
