@@ -157,6 +157,44 @@ int gf2_rref(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int32_t *rank,
              gf2_mat R_out, const gf2_sched *s, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Linear systems from a PLS (the decomposition as the building block for
+ * solving systems of linear equations: abstract and Section 1).  With P A = L S,
+ * A X = B becomes L S X = P B: Y = P B, forward substitution with L's unit lower
+ * r x r triangle on Y's first r rows, a consistency test on the remaining rows
+ * (Y_bottom = L_bottom Y_top), and back substitution with U_Q = S[:, Q].
+ *  A_pls, P, Q, rank  gf2_pls outputs (device; only read).
+ *  B      m x nrhs (device): column t is right-hand side t, so row i of B holds
+ *         equation i's entries of every right-hand side.  Only read.
+ *  X_out  n x nrhs (device): column t is a solution of A x = B[:, t] whose
+ *         non-pivot entries (columns not in Q[0, r)) are zero, when one exists.
+ *  bad    DEVICE uint64[ceil(nrhs / 64)]: bit t set when system t has no
+ *         solution (X_out's column t is then not a solution).
+ *  s      only the schur field is read (the substitutions' products).
+ * Asynchronous, rank read on the device; graph-capturable.  The transposition
+ * vector is turned into a row map on the device each call.
+ */
+size_t gf2_solve_workspace_bytes(int64_t m, int64_t n, int64_t nrhs);
+int gf2_solve(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *P, const int32_t *Q,
+              const int32_t *rank, gf2_mat B, gf2_mat X_out, uint64_t *bad,
+              const gf2_sched *s, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Basis of the null space {x : A x = 0} from a PLS (A x = 0 exactly when
+ * S x = 0, since P and L are injective on the rows that matter).  One basis
+ * vector per non-pivot column f, in increasing order of f: x[f] = 1, the other
+ * non-pivot entries 0, x[Q] = U_Q^{-1} S[:, f] -- the non-pivot columns of the
+ * reduced row echelon form, transposed.
+ *  A_pls, Q, rank  gf2_pls outputs (device; only read).
+ *  K_out  n x n (device, its own buffer): rows [0, n - r) receive the basis
+ *         vectors as packed rows, rows [n - r, n) are zeroed.
+ *  s      only the schur field is read.
+ * Asynchronous, rank read on the device; graph-capturable.
+ */
+size_t gf2_kernel_basis_workspace_bytes(int64_t m, int64_t n);
+int gf2_kernel_basis(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int32_t *rank,
+                     gf2_mat K_out, const gf2_sched *s, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Batched PLS: `count` independent matrices of any shapes up to
  * GF2_BATCH_MAX_M x GF2_BATCH_MAX_N, each decomposed in place exactly as
  * gf2_pls does (the result of Gaussian PLS, Appendix A).  One persistent launch

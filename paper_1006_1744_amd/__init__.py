@@ -17,7 +17,7 @@ import torch
 
 from .build import LIB as _LIB_PATH
 
-__all__ = ["Sched", "Mat", "get_lib", "default_sched", "pls", "pls_noalloc", "rref", "addmul", "to_device",
+__all__ = ["Sched", "Mat", "get_lib", "default_sched", "pls", "pls_noalloc", "rref", "solve", "kernel_basis", "addmul", "to_device",
            "to_host", "workspace", "Batch", "SCHUR_XOR", "SCHUR_MFMA", "SCHUR_FP4", "GF2Error"]
 
 SCHUR_XOR = 0
@@ -93,6 +93,14 @@ def _load():
     L.gf2_rref_workspace_bytes.restype = sz
     L.gf2_rref.argtypes = [vp, Mat, vp, vp, Mat, ctypes.POINTER(Sched), vp, sz, vp]
     L.gf2_rref.restype = i32
+    L.gf2_solve_workspace_bytes.argtypes = [i64, i64, i64]
+    L.gf2_solve_workspace_bytes.restype = sz
+    L.gf2_solve.argtypes = [vp, Mat, vp, vp, vp, Mat, Mat, vp, ctypes.POINTER(Sched), vp, sz, vp]
+    L.gf2_solve.restype = i32
+    L.gf2_kernel_basis_workspace_bytes.argtypes = [i64, i64]
+    L.gf2_kernel_basis_workspace_bytes.restype = sz
+    L.gf2_kernel_basis.argtypes = [vp, Mat, vp, vp, Mat, ctypes.POINTER(Sched), vp, sz, vp]
+    L.gf2_kernel_basis.restype = i32
     L.gf2_pls_batched_workspace_bytes.argtypes = [i64]
     L.gf2_pls_batched_workspace_bytes.restype = sz
     L.gf2_pls_batched.argtypes = [vp, vp, i64, vp, vp, ctypes.POINTER(Sched), vp, sz, vp]
@@ -455,6 +463,45 @@ def rref(A_pls: torch.Tensor, m: int, n: int, Q: torch.Tensor, rank: torch.Tenso
                               _mat(R, m, n), ctypes.byref(s) if s is not None else None,
                               ws.data_ptr(), ws.numel(), _stream(stream)))
     return R
+
+
+def solve(A_pls: torch.Tensor, m: int, n: int, P: torch.Tensor, Q: torch.Tensor,
+          rank: torch.Tensor, B: torch.Tensor, nrhs: int, X: torch.Tensor | None = None,
+          bad: torch.Tensor | None = None, ws: torch.Tensor | None = None, s: Sched | None = None,
+          stream=None):
+    """Solve A X = B from A's PLS (gf2_solve).  B: (m, stride) int64 CUDA tensor of
+    nrhs packed columns.  Returns (X (n, ceil(nrhs/64)) int64, bad int64 bit mask of
+    the inconsistent right-hand sides), asynchronous."""
+    dev = A_pls.device
+    nrw = max((nrhs + 63) // 64, 1)
+    X = torch.empty((max(n, 1), nrw), dtype=torch.int64, device=dev)[:n] if X is None else X
+    bad = torch.empty(nrw, dtype=torch.int64, device=dev) if bad is None else bad
+    nb = int(get_lib().gf2_solve_workspace_bytes(m, n, nrhs))
+    if ws is None or ws.numel() < nb:
+        ws = workspace(nb, dev)
+    _check(get_lib().gf2_solve(ctx(dev.index), _mat(A_pls, m, n), P.data_ptr(), Q.data_ptr(),
+                               rank.data_ptr(), _mat(B, m, nrhs), _mat(X, n, nrhs), bad.data_ptr(),
+                               ctypes.byref(s) if s is not None else None, ws.data_ptr(),
+                               ws.numel(), _stream(stream)))
+    return X, bad
+
+
+def kernel_basis(A_pls: torch.Tensor, m: int, n: int, Q: torch.Tensor, rank: torch.Tensor,
+                 K: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+                 s: Sched | None = None, stream=None) -> torch.Tensor:
+    """Null-space basis from A's PLS (gf2_kernel_basis): (n, ceil(n/64)) int64 whose
+    first n - rank rows are the basis vectors, the rest zero."""
+    dev = A_pls.device
+    nw = max((n + 63) // 64, 1)
+    K = torch.empty((max(n, 1), nw), dtype=torch.int64, device=dev)[:n] if K is None else K
+    nb = int(get_lib().gf2_kernel_basis_workspace_bytes(m, n))
+    if ws is None or ws.numel() < nb:
+        ws = workspace(nb, dev)
+    _check(get_lib().gf2_kernel_basis(ctx(dev.index), _mat(A_pls, m, n), Q.data_ptr(),
+                                      rank.data_ptr(), _mat(K, n, n),
+                                      ctypes.byref(s) if s is not None else None, ws.data_ptr(),
+                                      ws.numel(), _stream(stream)))
+    return K
 
 
 def addmul(C: torch.Tensor, A: torch.Tensor, B: torch.Tensor, m: int, k: int, n: int,

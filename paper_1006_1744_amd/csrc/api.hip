@@ -648,6 +648,232 @@ struct UpperSolve {
 };
 }  // namespace
 
+namespace {
+// Y <- L^{-1} Y for the unit lower triangle L of rows [0, r) of an in-place PLS
+// (strictly lower bits stored in columns [0, r)), nw words of right-hand sides:
+// recursive on row halves, the coupling block by one product, blocks of up to
+// 1024 rows by the blocked table solve.  Launched for rmax rows; the kernels
+// clip to ext[1] = r on the device.
+struct LowerSolve {
+    gf2_ctx *ctx;
+    uint64_t *Y;
+    int64_t sy;
+    const uint64_t *L;
+    int64_t sl;
+    int rmax, nw, schur;
+    const int32_t *ext;
+    uint64_t *Bt;
+    hipStream_t st;
+    hipError_t err = hipSuccess;
+    void chk(hipError_t e) {
+        if (err == hipSuccess && e != hipSuccess) err = e;
+    }
+    void solve(int a, int sz) {
+        if (a >= rmax || sz <= 0) return;
+        if (sz <= trsm_block_max_rows()) {
+            chk(launch_trsm_block(Y, sy, L, sl, rmax, row_range(-1, 1, a, sz), a / 64, 0, nw, ext, 1,
+                                  (sz + 63) / 64, nullptr, nullptr, 0, 0, st));
+            return;
+        }
+        const int h = (sz / 64 / 2) * 64;
+        solve(a, h);
+        chk(enqueue_gemm(ctx, Y, sy, L, sl, Y, sy, rmax, rmax, row_range(-1, 1, a + h, sz - h), a / 64,
+                         0, nw, row_range(-1, 1, a, h), h, schur, ext, Bt, st));
+        solve(a + h, sz - h);
+    }
+};
+
+// Workspace of gf2_solve.
+struct SolveLayout {
+    size_t ext, rr, perm, cnt, off, fill, list, y, pm, nm, pp, pn, uc, bt, total;
+    int64_t su, sy;
+    int rmax, nw, nrw;
+};
+
+SolveLayout solve_layout(int64_t m, int64_t n, int64_t nrhs) {
+    SolveLayout L;
+    L.nw = (int)std::max<int64_t>((n + 63) / 64, 1);
+    L.nrw = (int)std::max<int64_t>((nrhs + 63) / 64, 1);
+    L.rmax = (int)std::min(m, n);
+    L.su = std::max<int64_t>((L.rmax + 63) / 64, 1);
+    L.sy = L.nrw;
+    const size_t mm = (size_t)std::max<int64_t>(m, 1);
+    size_t off = 0;
+    L.ext = off; off = align_up(off + 16);
+    L.rr = off; off = align_up(off + 16);
+    L.perm = off; off = align_up(off + mm * 4);
+    L.cnt = off; off = align_up(off + mm * 4);
+    L.off = off; off = align_up(off + (mm + 1) * 4);
+    L.fill = off; off = align_up(off + mm * 4);
+    L.list = off; off = align_up(off + (size_t)std::max(L.rmax, 1) * 4);
+    L.y = off; off = align_up(off + mm * L.sy * 8);
+    L.pm = off; off = align_up(off + (size_t)L.nw * 8);
+    L.nm = off; off = align_up(off + (size_t)L.nw * 8);
+    L.pp = off; off = align_up(off + (size_t)(L.nw + 1) * 4);
+    L.pn = off; off = align_up(off + (size_t)(L.nw + 1) * 4);
+    L.uc = off; off = align_up(off + (size_t)std::max(L.rmax, 1) * L.su * 8);
+    L.bt = off; off = align_up(off + gemm_bt_words(L.nrw, std::max(L.rmax, 64)) * 8);
+    L.total = off;
+    return L;
+}
+
+// Workspace of gf2_kernel_basis.
+struct KernelLayout {
+    size_t rr, pm, nm, pp, pn, uc, xc, bt, xt, total;
+    int64_t su, sx, sxt;
+    int rmax, nw;
+};
+
+KernelLayout kernel_layout(int64_t m, int64_t n) {
+    KernelLayout L;
+    L.nw = (int)std::max<int64_t>((n + 63) / 64, 1);
+    L.rmax = (int)std::min(m, n);
+    L.su = std::max<int64_t>((L.rmax + 63) / 64, 1);
+    L.sx = L.nw;
+    L.sxt = L.su;
+    size_t off = 0;
+    L.rr = off; off = align_up(off + 16);
+    L.pm = off; off = align_up(off + (size_t)L.nw * 8);
+    L.nm = off; off = align_up(off + (size_t)L.nw * 8);
+    L.pp = off; off = align_up(off + (size_t)(L.nw + 1) * 4);
+    L.pn = off; off = align_up(off + (size_t)(L.nw + 1) * 4);
+    L.uc = off; off = align_up(off + (size_t)std::max(L.rmax, 1) * L.su * 8);
+    L.xc = off; off = align_up(off + (size_t)std::max(L.rmax, 1) * L.sx * 8);
+    L.bt = off;
+    off = align_up(off + gemm_bt_words(L.nw, std::max(64, (L.rmax / 64 / 2 + 1) * 64)) * 8);
+    L.xt = off; off = align_up(off + (size_t)64 * L.nw * L.sxt * 8);
+    L.total = off;
+    return L;
+}
+}  // namespace
+
+extern "C" size_t gf2_solve_workspace_bytes(int64_t m, int64_t n, int64_t nrhs) {
+    if (m < 0 || n < 0 || nrhs < 0 || m > kMaxDim || n > kMaxDim || nrhs > kMaxDim) return 0;
+    return solve_layout(m, n, nrhs).total;
+}
+
+extern "C" int gf2_solve(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *P, const int32_t *Q,
+                         const int32_t *rank, gf2_mat B, gf2_mat X_out, uint64_t *bad,
+                         const gf2_sched *s, void *ws, size_t ws_bytes, void *stream) {
+    if (!ctx) return GF2_E_ARG;
+    int rc;
+    if ((rc = check_mat(A_pls)) != GF2_OK) return rc;
+    if ((rc = check_mat(B)) != GF2_OK) return rc;
+    if ((rc = check_mat(X_out)) != GF2_OK) return rc;
+    if (B.m != A_pls.m || X_out.m != A_pls.n || X_out.n != B.n) return GF2_E_ARG;
+    if (!rank || (A_pls.m > 0 && !P) || (A_pls.n > 0 && !Q) || (B.n > 0 && !bad)) return GF2_E_ARG;
+    if (((uintptr_t)bad & 7) != 0) return GF2_E_ALIGN;
+    const gf2_sched ss = s ? *s : default_sched();
+    if (!sched_ok(&ss)) return GF2_E_ARG;
+    SolveLayout L = solve_layout(A_pls.m, A_pls.n, B.n);
+    if (!ws || ws_bytes < L.total) return GF2_E_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return GF2_E_ALIGN;
+    if (B.n == 0 || A_pls.n == 0) return GF2_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return GF2_E_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    char *base = (char *)ws;
+    const int m = (int)A_pls.m, n = (int)A_pls.n, nrw = (int)((B.n + 63) / 64);
+    int32_t *ext = (int32_t *)(base + L.ext), *rr = (int32_t *)(base + L.rr);
+    int32_t *perm = (int32_t *)(base + L.perm);
+    uint64_t *Y = (uint64_t *)(base + L.y);
+    uint64_t *PM = (uint64_t *)(base + L.pm), *NM = (uint64_t *)(base + L.nm);
+    int32_t *pp = (int32_t *)(base + L.pp), *pn = (int32_t *)(base + L.pn);
+    uint64_t *Uc = (uint64_t *)(base + L.uc), *Bt = (uint64_t *)(base + L.bt);
+    GF2_TRY(launch_solve_extents(rank, L.rmax, nrw, ext, st));
+    if (m > 0) {
+        // Y = P B
+        GF2_TRY(launch_perm_from_swaps(P, rank, m, L.rmax, (int32_t *)(base + L.cnt),
+                                       (int32_t *)(base + L.off), (int32_t *)(base + L.fill),
+                                       (int32_t *)(base + L.list), perm, st));
+        GF2_TRY(launch_gather_rows(Y, L.sy, B.words, B.stride, perm, m, nrw, st));
+        // forward substitution with L's unit lower triangle on rows [0, r)
+        LowerSolve fw{ctx, Y, L.sy, A_pls.words, A_pls.stride, L.rmax, nrw, ss.schur, ext, Bt, st};
+        fw.solve(0, (L.rmax + 63) / 64 * 64);
+        if (fw.err != hipSuccess) return GF2_E_HIP;
+        // rows [r, m): Y_bottom + L_bottom Y_top must vanish
+        GF2_TRY(enqueue_gemm(ctx, Y, L.sy, A_pls.words, A_pls.stride, Y, L.sy, m, m,
+                             row_range(1, -1, 0, kINF), 0, 0, nrw, row_range(-1, 1, 0, kINF),
+                             std::max(L.rmax, 1), ss.schur, ext, Bt, st));
+        GF2_TRY(launch_consistency(Y, L.sy, m, nrw, ext, bad, st));
+        // back substitution: U_Q = S[:, Q], Y_top <- U_Q^{-1} Y_top
+        GF2_TRY(launch_rref_masks(PM, NM, pp, pn, Q, rank, n, L.rmax, rr, st));
+        GF2_TRY(launch_rref_zero(Uc, L.su, nullptr, 0, L.rmax, ext, st));
+        GF2_TRY(launch_rref_gather(A_pls.words, A_pls.stride, Q, L.rmax, n, PM, NM, pp, pn, Uc, L.su,
+                                   nullptr, 0, ext, st));
+        UpperSolve bw;
+        bw.ctx = ctx;
+        bw.X = Y; bw.sx = L.sy; bw.U = Uc; bw.su = L.su;
+        bw.rmax = L.rmax; bw.nwmax = nrw; bw.schur = ss.schur;
+        bw.rr = ext; bw.Bt = Bt; bw.st = st;
+        bw.solve(0, (L.rmax + 63) / 64 * 64);
+        if (bw.err != hipSuccess) return GF2_E_HIP;
+    } else {
+        GF2_TRY(launch_zero_rows(bad, nrw, 1, nrw, st));
+        GF2_TRY(launch_zero_rows(PM, L.nw, 1, L.nw, st));
+        GF2_TRY(launch_fill_i32(pp, 0, L.nw + 1, st));
+    }
+    // X[Q[i]] = Y[i], the other rows zero
+    GF2_TRY(launch_solve_scatter(X_out.words, X_out.stride, n, nrw, Y, L.sy, PM, pp, st));
+    if (X_out.stride > nrw)
+        GF2_TRY(launch_zero_rows(X_out.words + nrw, X_out.stride, n, (int)(X_out.stride - nrw), st));
+    return GF2_OK;
+}
+
+extern "C" size_t gf2_kernel_basis_workspace_bytes(int64_t m, int64_t n) {
+    if (m < 0 || n < 0 || m > kMaxDim || n > kMaxDim) return 0;
+    return kernel_layout(m, n).total;
+}
+
+extern "C" int gf2_kernel_basis(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int32_t *rank,
+                                gf2_mat K_out, const gf2_sched *s, void *ws, size_t ws_bytes,
+                                void *stream) {
+    if (!ctx) return GF2_E_ARG;
+    int rc;
+    if ((rc = check_mat(A_pls)) != GF2_OK) return rc;
+    if ((rc = check_mat(K_out)) != GF2_OK) return rc;
+    if (K_out.m != A_pls.n || K_out.n != A_pls.n) return GF2_E_ARG;
+    if (!rank || (A_pls.n > 0 && !Q)) return GF2_E_ARG;
+    if (K_out.words == A_pls.words && A_pls.n > 0) return GF2_E_ARG;
+    const gf2_sched ss = s ? *s : default_sched();
+    if (!sched_ok(&ss)) return GF2_E_ARG;
+    KernelLayout L = kernel_layout(A_pls.m, A_pls.n);
+    if (!ws || ws_bytes < L.total) return GF2_E_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return GF2_E_ALIGN;
+    if (A_pls.n == 0) return GF2_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return GF2_E_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    char *base = (char *)ws;
+    const int n = (int)A_pls.n;
+    int32_t *rr = (int32_t *)(base + L.rr);
+    uint64_t *PM = (uint64_t *)(base + L.pm), *NM = (uint64_t *)(base + L.nm);
+    int32_t *pp = (int32_t *)(base + L.pp), *pn = (int32_t *)(base + L.pn);
+    uint64_t *Uc = (uint64_t *)(base + L.uc), *Xc = (uint64_t *)(base + L.xc);
+    uint64_t *XT = (uint64_t *)(base + L.xt);
+    // rank 0 with no rows (m == 0) still has every column free
+    GF2_TRY(launch_rref_masks(PM, NM, pp, pn, Q, rank, n, L.rmax, rr, st));
+    if (L.rmax > 0) {
+        // Xc = U_Q^{-1} S[:, N], the non-pivot columns of the RREF (as in gf2_rref)
+        GF2_TRY(launch_rref_zero(Uc, L.su, Xc, L.sx, L.rmax, rr, st));
+        GF2_TRY(launch_rref_gather(A_pls.words, A_pls.stride, Q, L.rmax, n, PM, NM, pp, pn, Uc, L.su,
+                                   Xc, L.sx, rr, st));
+        UpperSolve us;
+        us.ctx = ctx;
+        us.X = Xc; us.sx = L.sx; us.U = Uc; us.su = L.su;
+        us.rmax = L.rmax; us.nwmax = L.nw; us.schur = ss.schur;
+        us.rr = rr; us.Bt = (uint64_t *)(base + L.bt); us.st = st;
+        us.solve(0, (L.rmax + 63) / 64 * 64);
+        if (us.err != hipSuccess) return GF2_E_HIP;
+        // XT row j = column j of Xc over rows [0, r) (bits past r zero)
+        GF2_TRY(launch_transpose(Xc, L.sx, L.rmax, row_range(-1, 1, 0, kINF), 0, L.nw, L.rmax, XT,
+                                 L.sxt, rr, st, rr + 2));
+    }
+    GF2_TRY(launch_kernel_scatter(K_out.words, K_out.stride, n, XT, L.sxt, PM, NM, pp, pn, rr, st));
+    const int nw = (n + 63) / 64;
+    if (K_out.stride > nw)
+        GF2_TRY(launch_zero_rows(K_out.words + nw, K_out.stride, n, (int)(K_out.stride - nw), st));
+    return GF2_OK;
+}
+
 extern "C" size_t gf2_rref_workspace_bytes(int64_t m, int64_t n) {
     if (m < 0 || n < 0 || m > kMaxDim || n > kMaxDim) return 0;
     return rref_layout(m, n).total;

@@ -148,6 +148,31 @@ hipError_t launch_rref_scatter(uint64_t *R, int64_t sr, int m, int n, const int3
                                const int32_t *rr, const uint64_t *NM, const int32_t *prefN,
                                const uint64_t *Xc, int64_t sx, hipStream_t st);
 
+// Solver and null-space kernels (k_solve.hip).
+// perm[i] = the original row at position i after the transpositions P[0, r)
+// (r = *rank clamped to [0, rmax]); cnt, fill: int32[m], off: int32[m + 1],
+// list: int32[rmax] scratch.
+hipError_t launch_perm_from_swaps(const int32_t *P, const int32_t *rank, int m, int rmax,
+                                  int32_t *cnt, int32_t *off, int32_t *fill, int32_t *list,
+                                  int32_t *perm, hipStream_t st);
+// Y[i] <- B[perm[i]], m rows of nrw words.
+hipError_t launch_gather_rows(uint64_t *Y, int64_t sy, const uint64_t *B, int64_t sb,
+                              const int32_t *perm, int m, int nrw, hipStream_t st);
+// ext = {0, r, nrw}.
+hipError_t launch_solve_extents(const int32_t *rank, int rmax, int nrw, int32_t *ext,
+                                hipStream_t st);
+// bad[0, nrw) <- OR of Y rows [ext[1], m).
+hipError_t launch_consistency(const uint64_t *Y, int64_t sy, int m, int nrw, const int32_t *ext,
+                              uint64_t *bad, hipStream_t st);
+// X row j <- Y row i when j is the i-th pivot column (PM, prefP), else zero.
+hipError_t launch_solve_scatter(uint64_t *X, int64_t sx, int n, int nrw, const uint64_t *Y,
+                                int64_t sy, const uint64_t *PM, const int32_t *prefP,
+                                hipStream_t st);
+// Null-space basis rows from the transposed solved block XT (rows n x n).
+hipError_t launch_kernel_scatter(uint64_t *K, int64_t sk, int n, const uint64_t *XT, int64_t sxt,
+                                 const uint64_t *PM, const uint64_t *NM, const int32_t *prefP,
+                                 const int32_t *prefN, const int32_t *ext, hipStream_t st);
+
 // Batched PLS (k_batch.hip): queue order, then one persistent launch of `grid`
 // blocks.  ws holds batch_ws_bytes(count) bytes.
 size_t batch_ws_bytes(int64_t count);

@@ -109,11 +109,12 @@ __device__ inline void or_bits(uint64_t *row, int off, int cnt, uint64_t v) {
 // it) compressed by PM into Uc and by NM into Xc.  Uc, Xc zero on entry.  One
 // thread per (row, word), the word index fastest, so neighbouring threads read
 // neighbouring words of a row and OR into neighbouring words of its compact rows.
+// Xc == nullptr: U_Q alone (the solver needs it whatever the non-pivot columns).
 __global__ void rref_gather_kernel(const uint64_t *Ap, int64_t sap, const int32_t *Q, int nw,
                                    const uint64_t *PM, const uint64_t *NM, const int32_t *prefP,
                                    const int32_t *prefN, uint64_t *Uc, int64_t su, uint64_t *Xc,
                                    int64_t sx, const int32_t *rr) {
-    if (rr[2] == 0) return;   // no non-pivot column: nothing to solve
+    if (Xc && rr[2] == 0) return;   // no non-pivot column: nothing to solve
     const int r = rr[1];
     const int64_t total = (int64_t)r * nw;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -131,7 +132,7 @@ __global__ void rref_gather_kernel(const uint64_t *Ap, int64_t sap, const int32_
             x = (x & above) | (1ull << qb);
         }
         if (cpp) or_bits(Uc + (int64_t)i * su, prefP[w], cpp, pext64(x, pm));
-        if (cnn) or_bits(Xc + (int64_t)i * sx, prefN[w], cnn, pext64(x, nm));
+        if (cnn && Xc) or_bits(Xc + (int64_t)i * sx, prefN[w], cnn, pext64(x, nm));
     }
 }
 
@@ -164,11 +165,12 @@ __global__ void rref_scatter_kernel(uint64_t *R, int64_t sr, int m, const int32_
 }
 
 // Uc rows [0, r) x ceil(r / 64) words and Xc rows [0, r) x rr[2] words <- 0
-// (nothing when there is no non-pivot column).
+// (nothing when there is no non-pivot column; Uc alone when Xc is null).
 __global__ void rref_zero_kernel(uint64_t *Uc, int64_t su, uint64_t *Xc, int64_t sx,
                                  const int32_t *rr) {
-    const int r = rr[1], nx = rr[2], nu = (r + 63) / 64;
-    if (nx == 0) return;
+    const int r = rr[1], nu = (r + 63) / 64;
+    const int nx = Xc ? rr[2] : 0;
+    if (Xc && nx == 0) return;
     const int64_t tu = (int64_t)r * nu, total = tu + (int64_t)r * nx;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
