@@ -157,6 +157,44 @@ int gf2_rref(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int32_t *rank,
              gf2_mat R_out, const gf2_sched *s, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * M4RI (Section 3.1, algorithm "M4RI"; GaussSubmatrix, MakeTable and
+ * AddRowsFromTable of Appendix A): the reduced row echelon form directly, strip
+ * by strip, every row above and below a strip's pivot rows reduced through
+ * Gray-code tables of those rows.  Strips are 64-column panels; the schedule's
+ * k and tables set the table width and the tables per pass (cutoff and schur
+ * are not used).
+ *  A      m x n (device), overwritten with its RREF: rows < r in reduced echelon
+ *         form with leading ones at Q[0, r), rows >= r zero.
+ *  Q      DEVICE int32[n]: the pivot columns Q[0, r), then Q[i] = i.
+ *  rank   DEVICE int32: r.
+ * Asynchronous; graph-capturable.  The result equals gf2_rref of gf2_pls of A
+ * (the reduced row echelon form is unique).
+ */
+size_t gf2_m4ri_workspace_bytes(int64_t m, int64_t n);
+int gf2_m4ri(gf2_ctx *ctx, gf2_mat A, int32_t *Q, int32_t *rank, const gf2_sched *s, void *ws,
+             size_t ws_bytes, void *stream);
+
+/*
+ * The "M+P" hybrid of Section 6: M4RI strips while the approximated density of
+ * the part left to eliminate (rows without a pivot, columns from the next strip
+ * on) stays below `threshold` (the paper uses 0.15 and 0.20), then PLS
+ * (Sections 4-5, the schedule's cutoff and Schur product) and the RREF from it
+ * on that part, and finally the rows above it reduced by the part's RREF rows
+ * (one product).  The density is estimated from up to 256 rows spread evenly
+ * over the remaining rows, before every strip.
+ *  A, Q, rank   as gf2_m4ri (A receives its RREF).
+ *  switch_panel HOST int32 (nullable): the strip at which PLS took over, or -1
+ *               when M4RI finished alone.
+ * Threshold 0 runs PLS + RREF only; a threshold above 1 runs M4RI only.
+ * Synchronous: the call reads each density estimate back to choose the kernels
+ * that follow, so it waits on `stream` and cannot be captured in a graph.
+ */
+size_t gf2_rref_mp_workspace_bytes(int64_t m, int64_t n, const gf2_sched *s);
+int gf2_rref_mp(gf2_ctx *ctx, gf2_mat A, int32_t *Q, int32_t *rank, float threshold,
+                int32_t *switch_panel, const gf2_sched *s, void *ws, size_t ws_bytes,
+                void *stream);
+
+/*
  * Linear systems from a PLS (the decomposition as the building block for
  * solving systems of linear equations: abstract and Section 1).  With P A = L S,
  * A X = B becomes L S X = P B: Y = P B, forward substitution with L's unit lower

@@ -17,7 +17,7 @@ import torch
 
 from .build import LIB as _LIB_PATH
 
-__all__ = ["Sched", "Mat", "get_lib", "default_sched", "pls", "pls_noalloc", "rref", "solve", "kernel_basis", "addmul", "to_device",
+__all__ = ["Sched", "Mat", "get_lib", "default_sched", "pls", "pls_noalloc", "rref", "solve", "kernel_basis", "m4ri", "rref_mp", "addmul", "to_device",
            "to_host", "workspace", "Batch", "SCHUR_XOR", "SCHUR_MFMA", "SCHUR_FP4", "GF2Error"]
 
 SCHUR_XOR = 0
@@ -93,6 +93,15 @@ def _load():
     L.gf2_rref_workspace_bytes.restype = sz
     L.gf2_rref.argtypes = [vp, Mat, vp, vp, Mat, ctypes.POINTER(Sched), vp, sz, vp]
     L.gf2_rref.restype = i32
+    L.gf2_m4ri_workspace_bytes.argtypes = [i64, i64]
+    L.gf2_m4ri_workspace_bytes.restype = sz
+    L.gf2_m4ri.argtypes = [vp, Mat, vp, vp, ctypes.POINTER(Sched), vp, sz, vp]
+    L.gf2_m4ri.restype = i32
+    L.gf2_rref_mp_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(Sched)]
+    L.gf2_rref_mp_workspace_bytes.restype = sz
+    L.gf2_rref_mp.argtypes = [vp, Mat, vp, vp, ctypes.c_float, ctypes.POINTER(ctypes.c_int32),
+                              ctypes.POINTER(Sched), vp, sz, vp]
+    L.gf2_rref_mp.restype = i32
     L.gf2_solve_workspace_bytes.argtypes = [i64, i64, i64]
     L.gf2_solve_workspace_bytes.restype = sz
     L.gf2_solve.argtypes = [vp, Mat, vp, vp, vp, Mat, Mat, vp, ctypes.POINTER(Sched), vp, sz, vp]
@@ -463,6 +472,43 @@ def rref(A_pls: torch.Tensor, m: int, n: int, Q: torch.Tensor, rank: torch.Tenso
                               _mat(R, m, n), ctypes.byref(s) if s is not None else None,
                               ws.data_ptr(), ws.numel(), _stream(stream)))
     return R
+
+
+def m4ri(A: torch.Tensor, m: int, n: int, s: Sched | None = None, Q: torch.Tensor | None = None,
+         rank: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None):
+    """M4RI (gf2_m4ri): A is replaced by its RREF.  Returns (Q, rank) int32 CUDA
+    tensors (pivot columns first), asynchronous."""
+    dev = A.device
+    Q = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if Q is None else Q
+    rank = torch.empty(1, dtype=torch.int32, device=dev) if rank is None else rank
+    nb = int(get_lib().gf2_m4ri_workspace_bytes(m, n))
+    if ws is None or ws.numel() < nb:
+        ws = workspace(nb, dev)
+    _check(get_lib().gf2_m4ri(ctx(dev.index), _mat(A, m, n), Q.data_ptr(), rank.data_ptr(),
+                              ctypes.byref(s) if s is not None else None, ws.data_ptr(), ws.numel(),
+                              _stream(stream)))
+    return Q[:n], rank
+
+
+def rref_mp(A: torch.Tensor, m: int, n: int, threshold: float = 0.15, s: Sched | None = None,
+            Q: torch.Tensor | None = None, rank: torch.Tensor | None = None,
+            ws: torch.Tensor | None = None, stream=None):
+    """The M+P hybrid (gf2_rref_mp): A is replaced by its RREF.  Returns (Q, rank,
+    switch panel or -1).  Waits on the stream (density checks)."""
+    dev = A.device
+    Q = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if Q is None else Q
+    rank = torch.empty(1, dtype=torch.int32, device=dev) if rank is None else rank
+    nb = int(get_lib().gf2_rref_mp_workspace_bytes(m, n, ctypes.byref(s) if s is not None else None))
+    if nb == 0:
+        raise GF2Error("invalid size or schedule")
+    if ws is None or ws.numel() < nb:
+        ws = workspace(nb, dev)
+    sw = ctypes.c_int32(-2)
+    _check(get_lib().gf2_rref_mp(ctx(dev.index), _mat(A, m, n), Q.data_ptr(), rank.data_ptr(),
+                                 float(threshold), ctypes.byref(sw),
+                                 ctypes.byref(s) if s is not None else None, ws.data_ptr(),
+                                 ws.numel(), _stream(stream)))
+    return Q[:n], rank, int(sw.value)
 
 
 def solve(A_pls: torch.Tensor, m: int, n: int, P: torch.Tensor, Q: torch.Tensor,

@@ -879,25 +879,14 @@ extern "C" size_t gf2_rref_workspace_bytes(int64_t m, int64_t n) {
     return rref_layout(m, n).total;
 }
 
-extern "C" int gf2_rref(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int32_t *rank,
-                        gf2_mat R_out, const gf2_sched *s, void *ws, size_t ws_bytes,
-                        void *stream) {
-    if (!ctx) return GF2_E_ARG;
-    int rc;
-    if ((rc = check_mat(A_pls)) != GF2_OK) return rc;
-    if ((rc = check_mat(R_out)) != GF2_OK) return rc;
-    if (R_out.m != A_pls.m || R_out.n != A_pls.n) return GF2_E_ARG;
-    if (!rank || (A_pls.n > 0 && !Q)) return GF2_E_ARG;
-    if (R_out.words == A_pls.words && A_pls.m > 0) return GF2_E_ARG;
-    const gf2_sched ss = s ? *s : default_sched();
-    if (!sched_ok(&ss)) return GF2_E_ARG;
-    RrefLayout L = rref_layout(A_pls.m, A_pls.n);
-    if (!ws || ws_bytes < L.total) return GF2_E_WORKSPACE;
-    if (((uintptr_t)ws & 255) != 0) return GF2_E_ALIGN;
+namespace {
+// The RREF sequence on validated arguments.  R_out may be A_pls itself (the
+// hybrid works in place): A_pls is last read by the gather, before the scatter
+// writes R.  zero_pad: clear R_out's words past ceil(n / 64) up to its stride.
+int rref_run(gf2_ctx *ctx, const gf2_mat &A_pls, const int32_t *Q, const int32_t *rank,
+             const gf2_mat &R_out, const gf2_sched &ss, const RrefLayout &L, char *base,
+             hipStream_t st, bool zero_pad) {
     if (A_pls.m == 0 || A_pls.n == 0) return GF2_OK;
-    if (hipSetDevice(ctx->device) != hipSuccess) return GF2_E_HIP;
-    hipStream_t st = (hipStream_t)stream;
-    char *base = (char *)ws;
     const int m = (int)A_pls.m, n = (int)A_pls.n;
     int32_t *rr = (int32_t *)(base + L.rr);
     uint64_t *PM = (uint64_t *)(base + L.pm), *NM = (uint64_t *)(base + L.nm);
@@ -917,10 +906,238 @@ extern "C" int gf2_rref(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int
     us.solve(0, (L.rmax + 63) / 64 * 64);
     if (us.err != hipSuccess) return GF2_E_HIP;
     GF2_TRY(launch_rref_scatter(R_out.words, R_out.stride, m, n, Q, rr, NM, pn, Xc, L.sx, st));
-    // zero the padding words of R past ceil(n/64)
     const int nw = (n + 63) / 64;
-    if (R_out.stride > nw)
+    if (zero_pad && R_out.stride > nw)
         GF2_TRY(launch_zero_rows(R_out.words + nw, R_out.stride, m, (int)(R_out.stride - nw), st));
+    return GF2_OK;
+}
+}  // namespace
+
+extern "C" int gf2_rref(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int32_t *rank,
+                        gf2_mat R_out, const gf2_sched *s, void *ws, size_t ws_bytes,
+                        void *stream) {
+    if (!ctx) return GF2_E_ARG;
+    int rc;
+    if ((rc = check_mat(A_pls)) != GF2_OK) return rc;
+    if ((rc = check_mat(R_out)) != GF2_OK) return rc;
+    if (R_out.m != A_pls.m || R_out.n != A_pls.n) return GF2_E_ARG;
+    if (!rank || (A_pls.n > 0 && !Q)) return GF2_E_ARG;
+    if (R_out.words == A_pls.words && A_pls.m > 0) return GF2_E_ARG;
+    const gf2_sched ss = s ? *s : default_sched();
+    if (!sched_ok(&ss)) return GF2_E_ARG;
+    RrefLayout L = rref_layout(A_pls.m, A_pls.n);
+    if (!ws || ws_bytes < L.total) return GF2_E_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return GF2_E_ALIGN;
+    if (A_pls.m == 0 || A_pls.n == 0) return GF2_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return GF2_E_HIP;
+    return rref_run(ctx, A_pls, Q, rank, R_out, ss, L, (char *)ws, (hipStream_t)stream, true);
+}
+
+// ------------------------------------------------------------------ M4RI
+namespace {
+struct M4riLayout {
+    size_t rk, info, rec, bbuf, p, dens, total;
+    int64_t bstride;
+    int nb;
+};
+
+M4riLayout m4ri_layout(int64_t m, int64_t n) {
+    M4riLayout L;
+    L.nb = (int)((n + 63) / 64);
+    L.bstride = std::max(L.nb, 1);
+    size_t off = 0;
+    L.rk = off; off = align_up(off + (size_t)(L.nb + 2) * 4);
+    L.info = off; off = align_up(off + panel_info_bytes());
+    L.rec = off; off = align_up(off + m4ri_rec_bytes());
+    L.bbuf = off; off = align_up(off + (size_t)64 * L.bstride * 8);
+    L.p = off; off = align_up(off + (size_t)std::max<int64_t>(m, 1) * 4);
+    L.dens = off; off = align_up(off + 16);
+    L.total = off;
+    return L;
+}
+
+// One M4RI strip (Section 3.1) on the 64-column panel p: the panel search and
+// its final pass (GaussSubmatrix's pivots, rows moved into place), the change
+// of basis to the reduced pivot rows, and the table-driven reduction of every
+// other row (MakeTable / AddRowsFromTable above and below).
+hipError_t m4ri_step(gf2_ctx *ctx, const gf2_mat &A, const M4riLayout &L, char *base,
+                     int32_t *Q, const gf2_sched &ss, int p, hipStream_t st) {
+    int32_t *rk = (int32_t *)(base + L.rk);
+    int32_t *info = (int32_t *)(base + L.info);
+    uint64_t *Bbuf = (uint64_t *)(base + L.bbuf);
+    const int m = (int)A.m, n = (int)A.n, nw = L.nb;
+    hipError_t e = launch_leaf(A.words, A.stride, A.words, A.stride, 0, (int)A.stride, m, n, p, rk, p,
+                               (int32_t *)(base + L.p), Q, info, Bbuf, L.bstride, p + 1, nw,
+                               nullptr, st);
+    if (e != hipSuccess) return e;
+    if ((e = launch_m4ri_prep(info, rk, p, base + L.rec, st)) != hipSuccess) return e;
+    return launch_m4ri_update(A.words, A.stride, m, p, rk, p, p + 1, nw, ss.k, ss.tables,
+                              (const uint64_t *)(base + L.info + panel_info_linv_offset()),
+                              base + L.rec, Bbuf, L.bstride, ctx->cus, st);
+}
+
+// Workspace of the hybrid: the M4RI part, then (for the switch to PLS on the
+// remaining block) a PLS workspace, an RREF workspace, P2, Q2, rank2, the
+// pivot masks of the block, the gathered pivot columns of the rows above, the
+// extents and the product's transposed operand.
+struct MpLayout {
+    M4riLayout m4;
+    size_t pls, rref, p2, q2, r2, pm, nm, pp, pn, rr, cbuf, ext, bt, total;
+    size_t pls_bytes, rref_bytes;
+    int64_t sc;
+};
+
+MpLayout mp_layout(int64_t m, int64_t n, const gf2_sched &s) {
+    MpLayout L;
+    L.m4 = m4ri_layout(m, n);
+    const int nb = L.m4.nb;
+    // the block left for PLS is at most m x (n - 64 p) for the panel p it starts
+    // at; every workspace term grows with both sizes
+    size_t pb = 0;
+    for (int p = 0; p < nb; p++) pb = std::max(pb, pls_layout(m, n - 64 * (int64_t)p, s).total);
+    L.pls_bytes = pb;
+    L.rref_bytes = rref_layout(m, n).total;
+    const int64_t rmax = std::min(m, n);
+    L.sc = std::max<int64_t>((rmax + 63) / 64, 1);
+    const size_t nwp = (size_t)std::max(nb, 1);
+    size_t off = L.m4.total;
+    L.pls = off; off = align_up(off + pb);
+    L.rref = off; off = align_up(off + L.rref_bytes);
+    L.p2 = off; off = align_up(off + (size_t)std::max<int64_t>(m, 1) * 4);
+    L.q2 = off; off = align_up(off + (size_t)std::max<int64_t>(n, 1) * 4);
+    L.r2 = off; off = align_up(off + 16);
+    L.pm = off; off = align_up(off + nwp * 8);
+    L.nm = off; off = align_up(off + nwp * 8);
+    L.pp = off; off = align_up(off + (nwp + 1) * 4);
+    L.pn = off; off = align_up(off + (nwp + 1) * 4);
+    L.rr = off; off = align_up(off + 16);
+    L.cbuf = off; off = align_up(off + (size_t)std::max<int64_t>(m, 1) * L.sc * 8);
+    L.ext = off; off = align_up(off + 16);
+    L.bt = off; off = align_up(off + gemm_bt_words((int)nwp, (int)std::max<int64_t>(rmax, 64)) * 8);
+    L.total = off;
+    return L;
+}
+
+int check_m4ri_args(gf2_ctx *ctx, const gf2_mat &A, const int32_t *Q, const int32_t *rank,
+                    const gf2_sched *s, gf2_sched *ss) {
+    if (!ctx) return GF2_E_ARG;
+    int rc = check_mat(A);
+    if (rc != GF2_OK) return rc;
+    *ss = s ? *s : default_sched();
+    if (!sched_ok(ss)) return GF2_E_ARG;
+    if (!rank || (A.n > 0 && !Q)) return GF2_E_ARG;
+    return GF2_OK;
+}
+}  // namespace
+
+extern "C" size_t gf2_m4ri_workspace_bytes(int64_t m, int64_t n) {
+    if (m < 0 || n < 0 || m > kMaxDim || n > kMaxDim) return 0;
+    return m4ri_layout(m, n).total;
+}
+
+extern "C" int gf2_m4ri(gf2_ctx *ctx, gf2_mat A, int32_t *Q, int32_t *rank, const gf2_sched *s,
+                        void *ws, size_t ws_bytes, void *stream) {
+    gf2_sched ss;
+    int rc = check_m4ri_args(ctx, A, Q, rank, s, &ss);
+    if (rc != GF2_OK) return rc;
+    M4riLayout L = m4ri_layout(A.m, A.n);
+    if (!ws || ws_bytes < L.total) return GF2_E_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return GF2_E_ALIGN;
+    if (hipSetDevice(ctx->device) != hipSuccess) return GF2_E_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    char *base = (char *)ws;
+    int32_t *rk = (int32_t *)(base + L.rk);
+    GF2_TRY(launch_fill_i32(rk, 0, L.nb + 1, st));
+    if (A.m > 0)
+        for (int p = 0; p < L.nb; p++) GF2_TRY(m4ri_step(ctx, A, L, base, Q, ss, p, st));
+    GF2_TRY(launch_finalize((int32_t *)(base + L.p), Q, rank, rk, L.nb, (int)A.m, (int)A.n, st));
+    return GF2_OK;
+}
+
+extern "C" size_t gf2_rref_mp_workspace_bytes(int64_t m, int64_t n, const gf2_sched *s) {
+    if (m < 0 || n < 0 || m > kMaxDim || n > kMaxDim) return 0;
+    const gf2_sched ss = s ? *s : default_sched();
+    if (!sched_ok(&ss)) return 0;
+    return mp_layout(m, n, ss).total;
+}
+
+extern "C" int gf2_rref_mp(gf2_ctx *ctx, gf2_mat A, int32_t *Q, int32_t *rank, float threshold,
+                           int32_t *switch_panel, const gf2_sched *s, void *ws, size_t ws_bytes,
+                           void *stream) {
+    gf2_sched ss;
+    int rc = check_m4ri_args(ctx, A, Q, rank, s, &ss);
+    if (rc != GF2_OK) return rc;
+    if (!(threshold >= 0.f)) return GF2_E_ARG;
+    MpLayout L = mp_layout(A.m, A.n, ss);
+    if (!ws || ws_bytes < L.total) return GF2_E_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return GF2_E_ALIGN;
+    if (hipSetDevice(ctx->device) != hipSuccess) return GF2_E_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    char *base = (char *)ws;
+    const M4riLayout &M = L.m4;
+    int32_t *rk = (int32_t *)(base + M.rk);
+    int32_t *dens = (int32_t *)(base + M.dens);
+    const int m = (int)A.m, n = (int)A.n;
+    GF2_TRY(launch_fill_i32(rk, 0, M.nb + 1, st));
+    int sw = -1, R = 0;
+    for (int p = 0; p < M.nb && m > 0; p++) {
+        // approximated density of what is left (Section 6), read back here: the
+        // switch decides which kernels follow
+        GF2_TRY(launch_m4ri_density(A.words, A.stride, m, n, p, rk, p, dens, st));
+        int32_t h[2];
+        GF2_TRY(hipMemcpyAsync(h, dens, sizeof h, hipMemcpyDeviceToHost, st));
+        GF2_TRY(hipStreamSynchronize(st));
+        float d;
+        std::memcpy(&d, &h[0], sizeof d);
+        R = h[1];
+        if (R >= m) {
+            // every row has its pivot: the remaining strips find none
+            GF2_TRY(launch_fill_i32(rk + p + 1, R, M.nb - p, st));
+            break;
+        }
+        if (d >= threshold) {
+            sw = p;
+            break;
+        }
+        GF2_TRY(m4ri_step(ctx, A, M, base, Q, ss, p, st));
+    }
+    if (switch_panel) *switch_panel = sw;
+    if (sw < 0) {
+        GF2_TRY(launch_finalize((int32_t *)(base + M.p), Q, rank, rk, M.nb, m, n, st));
+        return GF2_OK;
+    }
+    // PLS and its RREF on the remaining block: rows [R, m), columns [64 sw, n)
+    gf2_mat sub;
+    sub.words = A.words + (int64_t)R * A.stride + sw;
+    sub.m = m - R;
+    sub.n = n - 64 * (int64_t)sw;
+    sub.stride = A.stride;
+    int32_t *P2 = (int32_t *)(base + L.p2), *Q2 = (int32_t *)(base + L.q2);
+    int32_t *r2 = (int32_t *)(base + L.r2);
+    PlsLayout PL = pls_layout(sub.m, sub.n, ss);
+    if (PL.total > L.pls_bytes) return GF2_E_WORKSPACE;
+    if ((rc = pls_run(ctx, sub, P2, Q2, r2, ss, PL, base + L.pls, st)) != GF2_OK) return rc;
+    RrefLayout RL = rref_layout(sub.m, sub.n);
+    if (RL.total > L.rref_bytes) return GF2_E_WORKSPACE;
+    if ((rc = rref_run(ctx, sub, Q2, r2, sub, ss, RL, base + L.rref, st, false)) != GF2_OK) return rc;
+    int32_t *ext = (int32_t *)(base + L.ext);
+    GF2_TRY(launch_mp_finish(Q, rank, ext, Q2, r2, R, 64 * sw, n, st));
+    if (R > 0) {
+        // rows above: clear the block's pivot columns with the block's RREF rows,
+        // X_top += X_top[:, Q2] R2 (R2[:, Q2] = I)
+        const int nws = (int)((sub.n + 63) / 64);
+        const int rmax2 = (int)std::min(sub.m, sub.n);
+        uint64_t *PM = (uint64_t *)(base + L.pm), *NM = (uint64_t *)(base + L.nm);
+        int32_t *pp = (int32_t *)(base + L.pp), *pn = (int32_t *)(base + L.pn);
+        uint64_t *C = (uint64_t *)(base + L.cbuf);
+        GF2_TRY(launch_rref_masks(PM, NM, pp, pn, Q2, r2, (int)sub.n, rmax2, (int32_t *)(base + L.rr),
+                                  st));
+        GF2_TRY(launch_zero_rows(C, L.sc, R, (int)L.sc, st));
+        GF2_TRY(launch_gather_cols(A.words + sw, A.stride, R, nws, PM, pp, C, L.sc, st));
+        GF2_TRY(enqueue_gemm(ctx, A.words, A.stride, C, L.sc, A.words, A.stride, R, m,
+                             row_range(-1, -1, 0, kINF), 0, sw, nws, row_range(0, 1, 0, kINF),
+                             std::max(rmax2, 1), ss.schur, ext, (uint64_t *)(base + L.bt), st));
+    }
     return GF2_OK;
 }
 

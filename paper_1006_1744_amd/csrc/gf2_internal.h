@@ -173,6 +173,23 @@ hipError_t launch_kernel_scatter(uint64_t *K, int64_t sk, int n, const uint64_t 
                                  const uint64_t *PM, const uint64_t *NM, const int32_t *prefP,
                                  const int32_t *prefN, const int32_t *ext, hipStream_t st);
 
+// M4RI and the hybrid (k_m4ri.hip).  rec: m4ri_rec_bytes() of device scratch.
+size_t m4ri_rec_bytes();
+hipError_t launch_m4ri_prep(const int32_t *info, const int32_t *rk, int b, void *rec,
+                            hipStream_t st);
+hipError_t launch_m4ri_update(uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk, int b,
+                              int w_lo, int w_hi, int k, int tables, const uint64_t *linv,
+                              const void *rec, const uint64_t *Bbuf, int64_t bstride,
+                              int target_blocks, hipStream_t st);
+// out[0] = estimated density of rows [rk[b], m) x words [w0, nw) (float bits), out[1] = rk[b].
+hipError_t launch_m4ri_density(const uint64_t *A, int64_t stride, int m, int n, int w0,
+                               const int32_t *rk, int b, int32_t *out, hipStream_t st);
+// C rows [0, rows) <- the columns of X selected by PM, packed (C zero on entry).
+hipError_t launch_gather_cols(const uint64_t *X, int64_t sx, int rows, int nw, const uint64_t *PM,
+                              const int32_t *prefP, uint64_t *C, int64_t sc, hipStream_t st);
+hipError_t launch_mp_finish(int32_t *Q, int32_t *rank, int32_t *ext, const int32_t *Q2,
+                            const int32_t *rank2, int R, int c0, int n, hipStream_t st);
+
 // Batched PLS (k_batch.hip): queue order, then one persistent launch of `grid`
 // blocks.  ws holds batch_ws_bytes(count) bytes.
 size_t batch_ws_bytes(int64_t count);
