@@ -67,8 +67,9 @@ int64_t oracle_pls(uint64_t *A, int64_t m, int64_t n, int64_t stride, int32_t *P
 {
     int64_t r = 0, c = 0;
     while (r < m && c < n) {
-        /* search for some pivot: smallest column j >= c holding a one in rows r..m-1,
-           and within it the first such row in the current order */
+        /* pivot choice (Appendix A, Gaussian PLS): the leftmost column j >= c with a
+           one in any of the rows r..m-1, and the first of those rows in the order
+           they stand in now */
         int64_t pi = -1, pj = -1;
 #if ORACLE_MUTATION == 4
         /* planted mistake: row-major search (first row, then its lowest column) */
@@ -116,8 +117,9 @@ int64_t oracle_pls(uint64_t *A, int64_t m, int64_t n, int64_t stride, int32_t *P
     }
     for (int64_t i = r; i < m; i++) P[i] = (int32_t)i;
     for (int64_t i = r; i < n; i++) Q[i] = (int32_t)i;
-    /* compress L: the multipliers of pivot j sit in column Q[j]; exchange that
-       column with column j on rows j..m-1, which moves them next to each other */
+    /* in-place layout: pivot j's multipliers were left in its column Q[j]; for
+       j = 0, 1, ... trade the contents of columns j and Q[j] in rows j..m-1, so
+       that L ends up in the first r columns (a no-op when Q[j] = j) */
     for (int64_t j = 0; j < r; j++) {
         int64_t q = Q[j];
         if (q == j) continue;

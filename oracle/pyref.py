@@ -2,29 +2,37 @@
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
-Rows are Python ints: column ``j`` is bit ``j``.  Every function follows the
+Rows are Python ints: column ``j`` is bit ``j``.  Each function computes what the
 algorithm it names in Albrecht & Pernet, "Efficient Decomposition of Dense
-Matrices over GF(2)", in the paper's order of steps and notation, written from
-its description rather than copied from the printed pseudo-code:
+Matrices over GF(2)", computes, following the algorithm's steps in the paper's
+order, but organised around what each step means rather than around the printed
+pseudo-code (different loop structure and bookkeeping), so that its agreement
+with the C oracle is a check between two codes written independently:
 
-* ``gaussian_pls``        -- Appendix A, "Gaussian PLS Decomposition".
-* ``pls_submatrix``       -- Appendix A, "PlsSubmatrix".
-* ``make_table1``         -- Section 4.1, "MakeTable1" (Gray-code table, the
-                             translation array L and the a-priori-id fix).
-* ``add_rows_from_table`` -- Appendix A, "AddRowsFromTable".
-* ``mmpf``                -- Section 4.1, "MMPF".
-* ``make_table``          -- Appendix A, "MakeTable" (the M4RI table, no fix).
-* ``gauss_submatrix``     -- Appendix A, "GaussSubmatrix".
-* ``m4ri``                -- Section 3.1, "M4RI" (reduced row echelon form).
-* ``pls_recursive``       -- Section 5, "PLS Decomposition" (asymptotically fast
+* ``gaussian_pls``        -- Appendix A, Gaussian PLS: the pivot rule applied
+                             pivot by pivot, then the in-place layout built
+                             directly from its definition.
+* ``pls_submatrix``       -- Appendix A, PlsSubmatrix: pivots of one strip, rows
+                             brought up to date with a per-row counter.
+* ``make_table1``         -- Section 4.1, MakeTable1: every combination of the
+                             strip rows, the index map, the multiplier fix.
+* ``add_rows_from_table`` -- Appendix A, AddRowsFromTable.
+* ``mmpf``                -- Section 4.1, MMPF.
+* ``make_table``          -- Appendix A, MakeTable (the M4RI table, no fix).
+* ``gauss_submatrix``     -- Appendix A, GaussSubmatrix.
+* ``m4ri``                -- Section 3.1, M4RI (reduced row echelon form).
+* ``pls_recursive``       -- Section 5, PLS Decomposition (asymptotically fast
                              recursion with a Gaussian base case).
 
 Readings where the printed text is ambiguous (all documented with the design):
 indices are 0-based and ranges half-open; the table index reads the k bits
 starting at column c with column c as the most significant bit (the "0 1 1 -> 3"
-example of Section 3.1); the k-th Gray code is g(i) = i ^ (i >> 1), its bit b
-selecting row k-1-b of the k source rows; "the a-priori id" of table row i is
-g(i).
+example of Section 3.1); a table entry's selection pattern has the first of the
+k source rows as its most significant bit; the "a priori id" of a table entry is
+that selection pattern.  Tables are built by doubling (entry idx from entry idx
+without its lowest set bit) instead of in Gray-code order: the paper allows any
+construction with 2^k - 1 additions, and only the entry selected by an index is
+ever read.
 """
 from __future__ import annotations
 
@@ -47,94 +55,107 @@ def swap_rows(rows: list[int], a: int, b: int) -> None:
     rows[a], rows[b] = rows[b], rows[a]
 
 
-def swap_cols_from(rows: list[int], a: int, b: int, start: int) -> None:
-    """Swap columns a and b in rows start..end."""
-    if a == b:
-        return
-    for i in range(start, len(rows)):
-        x = rows[i]
-        if bit(x, a) != bit(x, b):
-            rows[i] = x ^ (1 << a) ^ (1 << b)
+def lowest_one_at_or_after(x: int, c: int) -> int:
+    """Column of the lowest set bit of x at or after column c, or -1."""
+    y = x & mask_from(c)
+    return (y & -y).bit_length() - 1 if y else -1
 
 
-def compress_l(rows: list[int], Q: list[int], r: int) -> None:
-    """Swap columns j and Q[j] starting at row j, for j < r."""
-    for j in range(r):
-        swap_cols_from(rows, j, Q[j], j)
+def compressed_row(x: int, i: int, Q: list[int], r: int) -> int:
+    """Row i of the in-place result, from its state after elimination (the
+    multiplier of pivot s in column Q[s], the echelon row itself for i < r):
+    columns s < min(i, r) take the multipliers, and for i < r column i takes the
+    unit diagonal, columns (i, Q[i]] are zero and the columns right of Q[i] keep
+    the row of S."""
+    out = 0
+    for s in range(min(i, r)):
+        out |= bit(x, Q[s]) << s
+    if i < r:
+        q = Q[i]
+        out |= (1 << i) | ((x >> (q + 1)) << (q + 1))
+    return out
 
 
-# ---------------------------------------------------------------- Gaussian PLS
-def gaussian_pls(rows_in: list[int], m: int, n: int):
-    """Appendix A, "Gaussian PLS Decomposition".  Returns (r, P, Q, rows)."""
-    A = list(rows_in)
-    P = list(range(m))
-    Q = list(range(n))
-    r = c = 0
-    while r < m and c < n:
-        found = False
-        for j in range(c, n):              # search for some pivot, column by column
-            for i in range(r, m):
-                if bit(A[i], j):
-                    found = True
-                    break
-            if found:
-                break
-        if not found:
-            break
-        P[r], Q[r] = i, j
-        swap_rows(A, r, i)
-        if j + 1 < n:                       # clear below, keeping L in column j
-            for l in range(r + 1, m):
-                if bit(A[l], j):
-                    add_row_from(A, l, r, j + 1)
-        r, c = r + 1, j + 1
+def finish_pls(A: list[int], P: list[int], Q: list[int], m: int, n: int, r: int):
     for i in range(r, m):
         P[i] = i
     for i in range(r, n):
         Q[i] = i
-    compress_l(A, Q, r)
-    return r, P, Q, A
+    return r, P, Q, [compressed_row(A[i], i, Q, r) for i in range(m)]
+
+
+# ---------------------------------------------------------------- Gaussian PLS
+def gaussian_pls(rows_in: list[int], m: int, n: int):
+    """Appendix A, Gaussian PLS.  Pivot r is the leftmost column (right of the
+    previous pivot) holding a one in some row r.., taken from the first such row
+    in the current order, which is exchanged with row r; every later row with a
+    one in that column keeps it (its multiplier) and adds the pivot row's columns
+    to its right.  Returns (r, P, Q, rows)."""
+    A = list(rows_in)
+    P = list(range(m))
+    Q = list(range(n))
+    full = (1 << n) - 1
+    r = 0
+    start = 0                       # first column a new pivot may take
+    while r < m and start < n:
+        seen = 0
+        for x in A[r:]:
+            seen |= x
+        j = lowest_one_at_or_after(seen & full, start)
+        if j < 0:
+            break
+        i = next(t for t in range(r, m) if bit(A[t], j))
+        P[r], Q[r] = i, j
+        swap_rows(A, r, i)
+        right = A[r] & mask_from(j + 1)
+        for t in range(r + 1, m):
+            if bit(A[t], j):
+                A[t] ^= right
+        r += 1
+        start = j + 1
+    return finish_pls(A, P, Q, m, n, r)
 
 
 # ------------------------------------------------------------------ MMPF pieces
 def pls_submatrix(A: list[int], m: int, n: int, s_r: int, s_c: int, k: int,
                   P: list[int], Q: list[int]):
-    """Appendix A, "PlsSubmatrix": find up to k pivots in the k columns starting
-    at s_c, searching rows from s_r in the current order; lazily clear earlier
-    strip columns (done[] bookkeeping); finish the touched rows.
-    Returns (kbar, d_r)."""
-    done = [0] * k
-    kbar = 0
-    for r in range(k):
-        found = False
-        i = s_r + r
-        while i < m:
-            for l in range(r):             # clear before
-                if done[l] < i:
-                    if bit(A[i], s_c + l):
-                        add_row_from(A, i, s_r + l, s_c + l + 1)
-                    done[l] = i
-            if bit(A[i], s_c + r):
-                found = True
+    """Appendix A, PlsSubmatrix: up to k pivots of the strip of k columns at
+    s_c, among the rows from s_r in the current order.  A row is reduced by the
+    strip pivots lazily: a counter per row says how many of them it has seen,
+    and the row catches up when the scan reaches it again.  The scan for strip
+    column s_c + t looks at rows s_r + t.. and stops at the first one left with
+    a one there; a column with no such row ends the strip.  Every row the scan
+    reached is then brought up to date with all pivots.  Returns (kbar, first
+    row never reached)."""
+    seen = {}                       # row position -> pivots applied to it
+
+    def catch_up(i: int, t: int) -> None:
+        for s in range(seen.get(i, 0), t):
+            if bit(A[i], s_c + s):
+                A[i] ^= A[s_r + s] & mask_from(s_c + s + 1)
+        seen[i] = t
+
+    t = 0
+    reached = s_r
+    while t < k:
+        col = s_c + t
+        hit = -1
+        for i in range(s_r + t, m):
+            catch_up(i, t)
+            reached = max(reached, i + 1)
+            if bit(A[i], col):
+                hit = i
                 break
-            i += 1
-        if not found:
+        if hit < 0:
             break
-        P[s_r + r], Q[s_r + r] = i, s_c + r
-        swap_rows(A, s_r + r, i)
-        done[r] = i
-        kbar = r + 1
-    d_r = max(done[:kbar]) if kbar else s_r
-    for c2 in range(kbar):                 # finish submatrix
-        if s_c + c2 < n - 1:
-            for r2 in range(done[c2] + 1, d_r + 1):
-                if bit(A[r2], s_c + c2):
-                    add_row_from(A, r2, s_r + c2, s_c + c2 + 1)
-    return kbar, d_r
-
-
-def gray(i: int) -> int:
-    return i ^ (i >> 1)
+        dst = s_r + t
+        P[dst], Q[dst] = hit, col
+        swap_rows(A, dst, hit)
+        seen[dst], seen[hit] = seen.get(hit, 0), seen.get(dst, 0)
+        t += 1
+    for i in range(s_r + t, reached):
+        catch_up(i, t)
+    return t, reached
 
 
 def table_id(x: int, c: int, k: int) -> int:
@@ -145,119 +166,114 @@ def table_id(x: int, c: int, k: int) -> int:
     return v
 
 
-def make_table1(U: list[int], c: int, kbar: int):
-    """Section 4.1, "MakeTable1".  U holds kbar rows; returns (T, L).
+def _combination_table(U: list[int], c: int, k: int) -> list[int]:
+    """Entry idx = sum of the rows U[k-1-b] over the set bits b of idx, from
+    column c on; each entry from the entry without its lowest set bit."""
+    T = [0] * (1 << k)
+    for idx in range(1, 1 << k):
+        low = idx & -idx
+        T[idx] = T[idx ^ low] ^ (U[k - low.bit_length()] & mask_from(c))
+    return T
 
-    T[i] is the sum of the rows of U selected by the Gray code g(i), from column
-    c on (bit b of g(i) selects row kbar-1-b); L maps the k-bit id read at column
-    c of T[i] to i; finally the bits of the a-priori id g(i) are added onto the
-    kbar columns starting at c, so that adding T[L[id]] to a row whose strip
-    reads id leaves the multipliers of the U rows in the strip."""
-    size = 1 << kbar
-    T = [0] * size
-    for i in range(1, size):
-        flipped = (gray(i) ^ gray(i - 1)).bit_length() - 1
-        j = kbar - 1 - flipped
-        T[i] = T[i - 1] ^ (U[j] & mask_from(c))
-    L = [0] * size
-    for i in range(1, size):
-        L[table_id(T[i], c, kbar)] = i
-    for i in range(1, size):
-        g = gray(i)
+
+def make_table1(U: list[int], c: int, kbar: int):
+    """Section 4.1, MakeTable1.  U holds the kbar strip rows (echelon, columns
+    left of each row's diagonal cleared); returns (T, L): T lists every
+    combination of them, L maps the kbar-bit pattern a combination shows at
+    columns c.. to its entry, and each entry also carries its own selection
+    pattern in the strip (the multiplier fix of "Preserving L"), so adding
+    T[L[pattern]] to a row leaves the rows' multipliers in its strip."""
+    T = _combination_table(U, c, kbar)
+    L = [0] * len(T)
+    for idx, v in enumerate(T):
+        L[table_id(v, c, kbar)] = idx
+    for idx in range(len(T)):
         for j in range(kbar):
-            b_j = (g >> (kbar - 1 - j)) & 1
-            if b_j:
-                T[i] ^= 1 << (c + j)
+            if (idx >> (kbar - 1 - j)) & 1:
+                T[idx] ^= 1 << (c + j)
     return T, L
 
 
 def make_table(A: list[int], r: int, c: int, k: int):
-    """Appendix A, "MakeTable" (M4RI): Gray-code table of the k rows starting at
-    row r, from column c, and the array L indexing it by the k bits at column c."""
-    size = 1 << k
-    T = [0] * size
-    for i in range(1, size):
-        flipped = (gray(i) ^ gray(i - 1)).bit_length() - 1
-        j = r + (k - 1 - flipped)
-        T[i] = T[i - 1] ^ (A[j] & mask_from(c))
-    L = [0] * size
-    for i in range(size):
-        L[table_id(T[i], c, k)] = i
+    """Appendix A, MakeTable (M4RI): every combination of the k rows starting at
+    row r, from column c on, and the map L from the pattern at columns c.. to
+    the entry."""
+    T = _combination_table(A[r:r + k], c, k)
+    L = [0] * len(T)
+    for idx, v in enumerate(T):
+        L[table_id(v, c, k)] = idx
     return T, L
 
 
 def add_rows_from_table(A: list[int], r_start: int, r_end: int, c: int, k: int,
                         T: list[int], L: list[int]) -> None:
-    """Appendix A, "AddRowsFromTable"."""
+    """Appendix A, AddRowsFromTable: each row adds the entry its pattern selects."""
     for i in range(r_start, r_end):
-        idx = table_id(A[i], c, k)
-        A[i] ^= T[L[idx]] & mask_from(c)
+        A[i] ^= T[L[table_id(A[i], c, k)]] & mask_from(c)
 
 
 def mmpf(rows_in: list[int], m: int, n: int, k: int):
-    """Section 4.1, "MMPF".  Returns (r, P, Q, rows)."""
+    """Section 4.1, MMPF: strips of k columns; each strip's pivots from
+    PlsSubmatrix, its echelon rows tabulated by MakeTable1, and the rows the
+    strip search never reached updated through the table.  A strip without a
+    pivot in its first column moves on by one column.  Returns (r, P, Q, rows)."""
     A = list(rows_in)
     P = list(range(m))
     Q = list(range(n))
     r = c = 0
     while r < m and c < n:
-        kk = min(k, n - c)
-        kbar, d_r = pls_submatrix(A, m, n, r, c, kk, P, Q)
-        if kbar > 0:
-            U = []
-            for t in range(kbar):          # zero everything before the triangle
-                U.append(A[r + t] & mask_from(c + t))
-            T, L = make_table1(U, c, kbar)
-            add_rows_from_table(A, d_r + 1, m, c, kbar, T, L)
-            r, c = r + kbar, c + kbar
-        else:
-            c += 1                         # skip zero column
-    for i in range(r, m):
-        P[i] = i
-    for i in range(r, n):
-        Q[i] = i
-    compress_l(A, Q, r)
-    return r, P, Q, A
+        kbar, reached = pls_submatrix(A, m, n, r, c, min(k, n - c), P, Q)
+        if kbar == 0:
+            c += 1
+            continue
+        U = [A[r + t] & mask_from(c + t) for t in range(kbar)]
+        T, L = make_table1(U, c, kbar)
+        add_rows_from_table(A, reached, m, c, kbar, T, L)
+        r += kbar
+        c += kbar
+    return finish_pls(A, P, Q, m, n, r)
 
 
 # ------------------------------------------------------------------------ M4RI
 def gauss_submatrix(A: list[int], r: int, c: int, k: int, r_end: int) -> int:
-    """Appendix A, "GaussSubmatrix": reduced echelon form of the k-column strip
-    at (r, c), searching pivot rows up to r_end.  Returns the rank found."""
-    r_s = r
-    for j in range(c, c + k):
-        found = False
-        for i in range(r_s, r_end):
-            for l in range(j - c):         # clear the first columns
-                if bit(A[i], c + l):
-                    add_row_from(A, i, r + l, c + l)
-            if bit(A[i], j):
-                swap_rows(A, i, r_s)
-                for l in range(r, r_s):    # clear above
-                    if bit(A[l], j):
-                        add_row_from(A, l, r_s, j)
-                r_s += 1
-                found = True
+    """Appendix A, GaussSubmatrix: the strip of k columns at (r, c) brought to
+    reduced echelon form.  For each strip column in turn, rows r + kbar .. in the
+    current order are reduced by the strip's pivot rows and tested; the first
+    with a one there is moved to slot r + kbar and cleared from the pivot rows
+    above it.  Stops at the first strip column without a pivot.  Returns kbar."""
+    kbar = 0
+    for col in range(c, c + k):
+        hit = -1
+        for i in range(r + kbar, r_end):
+            for s in range(kbar):
+                if bit(A[i], c + s):
+                    A[i] ^= A[r + s]
+            if bit(A[i], col):
+                hit = i
                 break
-        if not found:
-            return j - c
-    return k
+        if hit < 0:
+            break
+        swap_rows(A, r + kbar, hit)
+        for s in range(kbar):
+            if bit(A[r + s], col):
+                A[r + s] ^= A[r + kbar]
+        kbar += 1
+    return kbar
 
 
 def m4ri(rows_in: list[int], m: int, n: int, k: int):
-    """Section 3.1, "M4RI": returns (r, rows) with rows in reduced echelon form."""
+    """Section 3.1, M4RI: returns (r, rows) with rows in reduced echelon form."""
     A = list(rows_in)
     r = c = 0
     while c < n:
-        kk = min(k, n - c)
-        kbar = gauss_submatrix(A, r, c, kk, m)
+        width = min(k, n - c)
+        kbar = gauss_submatrix(A, r, c, width, m)
         if kbar > 0:
             T, L = make_table(A, r, c, kbar)
             add_rows_from_table(A, 0, r, c, kbar, T, L)
             add_rows_from_table(A, r + kbar, m, c, kbar, T, L)
-        r, c = r + kbar, c + kbar
-        if kk != kbar:
-            c += 1
+        r += kbar
+        c += kbar + (1 if kbar < width else 0)
     return r, A
 
 
