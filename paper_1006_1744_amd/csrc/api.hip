@@ -936,7 +936,7 @@ extern "C" int gf2_rref(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int
 // ------------------------------------------------------------------ M4RI
 namespace {
 struct M4riLayout {
-    size_t rk, info, rec, bbuf, p, dens, total;
+    size_t rk, info, rec, bbuf, p, dens, cbuf, total;
     int64_t bstride;
     int nb;
 };
@@ -952,6 +952,7 @@ M4riLayout m4ri_layout(int64_t m, int64_t n) {
     L.bbuf = off; off = align_up(off + (size_t)64 * L.bstride * 8);
     L.p = off; off = align_up(off + (size_t)std::max<int64_t>(m, 1) * 4);
     L.dens = off; off = align_up(off + 16);
+    L.cbuf = off; off = align_up(off + (size_t)std::max<int64_t>(m, 1) * 8);
     L.total = off;
     return L;
 }
@@ -973,7 +974,8 @@ hipError_t m4ri_step(gf2_ctx *ctx, const gf2_mat &A, const M4riLayout &L, char *
     if ((e = launch_m4ri_prep(info, rk, p, base + L.rec, st)) != hipSuccess) return e;
     return launch_m4ri_update(A.words, A.stride, m, p, rk, p, p + 1, nw, ss.k, ss.tables,
                               (const uint64_t *)(base + L.info + panel_info_linv_offset()),
-                              base + L.rec, Bbuf, L.bstride, ctx->cus, st);
+                              base + L.rec, (uint64_t *)(base + L.cbuf), Bbuf, L.bstride, ctx->cus,
+                              st);
 }
 
 // Workspace of the hybrid: the M4RI part, then (for the switch to PLS on the

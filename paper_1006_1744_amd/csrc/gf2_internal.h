@@ -177,10 +177,11 @@ hipError_t launch_kernel_scatter(uint64_t *K, int64_t sk, int n, const uint64_t 
 size_t m4ri_rec_bytes();
 hipError_t launch_m4ri_prep(const int32_t *info, const int32_t *rk, int b, void *rec,
                             hipStream_t st);
+// cbuf: m words of device scratch (the rows' multipliers).
 hipError_t launch_m4ri_update(uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk, int b,
                               int w_lo, int w_hi, int k, int tables, const uint64_t *linv,
-                              const void *rec, const uint64_t *Bbuf, int64_t bstride,
-                              int target_blocks, hipStream_t st);
+                              const void *rec, uint64_t *cbuf, const uint64_t *Bbuf,
+                              int64_t bstride, int target_blocks, hipStream_t st);
 // out[0] = estimated density of rows [rk[b], m) x words [w0, nw) (float bits), out[1] = rk[b].
 hipError_t launch_m4ri_density(const uint64_t *A, int64_t stride, int m, int n, int w0,
                                const int32_t *rk, int b, int32_t *out, hipStream_t st);

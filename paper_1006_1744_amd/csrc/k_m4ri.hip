@@ -23,6 +23,10 @@
 //    with no pivot is zero in every remaining row).
 // The tables of B (k rows each, `tables` per pass) are MakeTable's; one table
 // row per table and row is AddRowsFromTable.
+// Every row's multiplier (xs G or l L^{-1}) and new panel word are formed by
+// one kernel before the update, which reads the multipliers from a buffer: the
+// update's column tiles of one row run in different blocks, and none of them
+// may see the panel word after another has rewritten it.
 #include <algorithm>
 
 #include "gf2_device.h"
@@ -81,7 +85,7 @@ __global__ __launch_bounds__(64) void m4ri_prep_kernel(const PanelInfo *info, co
 
 constexpr int M4_THREADS = 1024;
 constexpr int M4_TWMAX = 8;
-constexpr int M4_TABLE_LDS = 88 * 1024;   // B tables; the rest (transform tables, tiles) stays below 50 KiB
+constexpr int M4_TABLE_LDS = 120 * 1024;   // the B tables of one pass
 constexpr int M4_LDS_MAX = 150 * 1024;
 
 int m4ri_tile_words(int k, int tables) {
@@ -90,22 +94,60 @@ int m4ri_tile_words(int k, int tables) {
 }
 
 size_t m4ri_lds_bytes(int k, int tables, int TW) {
-    return (size_t)(3 * 8 * 256 + 2 * 64 + 2 * 64 * TW + tables * (1 << k) * TW) * 8;
+    return (size_t)(64 + 2 * 64 * TW + tables * (1 << k) * TW) * 8;
 }
 
-// Every row but the pivot rows on the word tile [w0, w0 + TW) of [w_lo, w_hi),
-// blocks of blockIdx.y == 0 also on the panel word wc; block (0, y) writes the
-// pivot rows' results.  2^lg_tpr threads share a row (each its words).
+// Per row: the multiplier on the staged pivot rows B (rows above: xs G, rows
+// below: l L^{-1}) into cbuf, and the row's new panel word (above: xs ^ xs H,
+// below: zero, pivot row t: E_t).
+__global__ __launch_bounds__(M4_THREADS) void m4ri_mult_kernel(uint64_t *A, int64_t stride, int m,
+                                                               int wc, const int32_t *rk, int b,
+                                                               const uint64_t *linv,
+                                                               const M4riRec *rec, uint64_t *cbuf) {
+    __shared__ uint64_t sLT[8 * 256], sGT[8 * 256], sHT[8 * 256];
+    __shared__ uint64_t sRows[64];
+    const int R = rk[b];
+    const int r = rk[b + 1] - R;
+    if (r <= 0) return;
+    const int tid = threadIdx.x;
+    const uint64_t *srcs[3] = {linv, rec->G, rec->H};
+    uint64_t *dsts[3] = {sLT, sGT, sHT};
+    for (int u = 0; u < 3; u++) {
+        if (tid < 64) sRows[tid] = srcs[u][tid];
+        __syncthreads();
+        build_tables_8x8<M4_THREADS>(sRows, dsts[u], tid);
+    }
+    for (int i = blockIdx.x * M4_THREADS + tid; i < m; i += gridDim.x * M4_THREADS) {
+        uint64_t *px = A + (int64_t)i * stride + wc;
+        if (i >= R && i < R + r) {
+            *px = rec->E[i - R];
+            continue;
+        }
+        const uint64_t xs = *px;
+        const bool above = i < R;
+        const uint64_t *tt = above ? sGT : sLT;
+        uint64_t c = 0, h = 0;
+#pragma unroll
+        for (int g8 = 0; g8 < 8; g8++) {
+            const int byte = (int)((xs >> (8 * g8)) & 255);
+            c ^= tt[g8 * 256 + byte];
+            if (above) h ^= sHT[g8 * 256 + byte];
+        }
+        cbuf[i] = c;
+        const uint64_t ns = above ? (xs ^ h) : 0ull;
+        if (ns != xs) *px = ns;
+    }
+}
+
+// Every row but the pivot rows on the word tile [w0, w0 + TW) of [w_lo, w_hi):
+// x += c B with c = cbuf[row]; block (0, y) writes the pivot rows' results
+// N B.  2^lg_tpr threads share a row (each its words).
 __global__ __launch_bounds__(M4_THREADS) void m4ri_update_kernel(
-    uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk, int b, int w_lo, int w_hi,
-    int k, int tables, int TW, int lg_tpr, const uint64_t *linv, const M4riRec *rec,
-    const uint64_t *Bbuf, int64_t bstride) {
+    uint64_t *A, int64_t stride, int m, const int32_t *rk, int b, int w_lo, int w_hi, int k,
+    int tables, int TW, int lg_tpr, const M4riRec *rec, const uint64_t *cbuf, const uint64_t *Bbuf,
+    int64_t bstride) {
     extern __shared__ uint64_t m4_lds[];
-    uint64_t *sLT = m4_lds;              // [8][256] combinations of L^{-1} rows
-    uint64_t *sGT = sLT + 8 * 256;       // [8][256] of G rows
-    uint64_t *sHT = sGT + 8 * 256;       // [8][256] of H rows
-    uint64_t *sRows = sHT + 8 * 256;     // [64] staging of the 64-row inputs
-    uint64_t *sN = sRows + 64;           // [64]
+    uint64_t *sN = m4_lds;               // [64]
     uint64_t *sB = sN + 64;              // [64][TW]
     uint64_t *sU = sB + 64 * TW;         // [64][TW] pivot rows' results
     uint64_t *sT = sU + 64 * TW;         // [tables][1 << k][TW]
@@ -114,8 +156,8 @@ __global__ __launch_bounds__(M4_THREADS) void m4ri_update_kernel(
     if (r <= 0) return;
     const int tid = threadIdx.x;
     const int w0 = w_lo + blockIdx.y * TW;
-    const int tw_n = max(0, min(TW, w_hi - w0));
-    const bool strip = blockIdx.y == 0;
+    const int tw_n = min(TW, w_hi - w0);
+    if (tw_n <= 0) return;
     const bool pivots_here = blockIdx.x == 0;
     const int wq = tid % TW, pq = tid / TW, pstep = M4_THREADS / TW;
     if (tid < 64) sN[tid] = rec->N[tid];
@@ -125,14 +167,6 @@ __global__ __launch_bounds__(M4_THREADS) void m4ri_update_kernel(
                 (t < r && wq < tw_n) ? Bbuf[(int64_t)t * bstride + (w0 - w_lo) + wq] : 0ull;
             sU[t * TW + wq] = 0ull;
         }
-    // the three 64-row transforms, one at a time through sRows
-    const uint64_t *srcs[3] = {linv, rec->G, rec->H};
-    uint64_t *dsts[3] = {sLT, sGT, sHT};
-    for (int u = 0; u < 3; u++) {
-        if (tid < 64) sRows[tid] = srcs[u][tid];
-        __syncthreads();
-        build_tables_8x8<M4_THREADS>(sRows, dsts[u], tid);
-    }
     const int ng = (r + k - 1) / k;
     const int npass = (ng + tables - 1) / tables;
     const int esz = 1 << k;
@@ -149,18 +183,14 @@ __global__ __launch_bounds__(M4_THREADS) void m4ri_update_kernel(
     for (int chunk = 0; chunk < nchunks; chunk++, j += per) {
         const bool act = j < nrows;
         const int i = j < R ? j : j + r;
-        const bool above = i < R;
         uint64_t x[M4_TWMAX];
-        uint64_t xs = 0, c = 0;
+        uint64_t c = 0;
         uint64_t *px = A + (int64_t)i * stride + w0 + wb;
         if (act) {
-            xs = A[(int64_t)i * stride + wc];
+            c = cbuf[i];
 #pragma unroll
             for (int w = 0; w < M4_TWMAX; w++)
                 if (w < wn) x[w] = px[w];
-            const uint64_t *tt = above ? sGT : sLT;
-#pragma unroll
-            for (int g8 = 0; g8 < 8; g8++) c ^= tt[g8 * 256 + (int)((xs >> (8 * g8)) & 255)];
         }
         for (int pass = 0; pass < npass; pass++) {
             const int g0 = pass * tables, g1 = min(ng, g0 + tables);
@@ -192,23 +222,10 @@ __global__ __launch_bounds__(M4_THREADS) void m4ri_update_kernel(
 #pragma unroll
             for (int w = 0; w < M4_TWMAX; w++)
                 if (w < wn) px[w] = x[w];
-            if (strip && part == 0) {
-                uint64_t ns = 0;
-                if (above) {
-                    ns = xs;
-#pragma unroll
-                    for (int g8 = 0; g8 < 8; g8++)
-                        ns ^= sHT[g8 * 256 + (int)((xs >> (8 * g8)) & 255)];
-                }
-                if (ns != xs) A[(int64_t)i * stride + wc] = ns;
-            }
         }
     }
-    if (pivots_here) {
-        if (pq < pstep && wq < tw_n)
-            for (int t = pq; t < r; t += pstep) A[(int64_t)(R + t) * stride + w0 + wq] = sU[t * TW + wq];
-        if (strip && tid < r) A[(int64_t)(R + tid) * stride + wc] = rec->E[tid];
-    }
+    if (pivots_here && pq < pstep && wq < tw_n)
+        for (int t = pq; t < r; t += pstep) A[(int64_t)(R + t) * stride + w0 + wq] = sU[t * TW + wq];
 }
 
 // Estimated density of the rows [R, m) on the words [w0, nw) (the part left to
@@ -289,11 +306,18 @@ hipError_t launch_m4ri_prep(const int32_t *info, const int32_t *rk, int b, void 
 
 hipError_t launch_m4ri_update(uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk, int b,
                               int w_lo, int w_hi, int k, int tables, const uint64_t *linv,
-                              const void *rec, const uint64_t *Bbuf, int64_t bstride,
-                              int target_blocks, hipStream_t st) {
+                              const void *rec, uint64_t *cbuf, const uint64_t *Bbuf,
+                              int64_t bstride, int target_blocks, hipStream_t st) {
+    const M4riRec *rc = reinterpret_cast<const M4riRec *>(rec);
+    int mb = (m + M4_THREADS - 1) / M4_THREADS;
+    mb = std::max(1, std::min(mb, target_blocks));
+    hipLaunchKernelGGL(m4ri_mult_kernel, dim3(mb), dim3(M4_THREADS), 0, st, A, stride, m, wc, rk, b,
+                       linv, rc, cbuf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || w_hi <= w_lo) return e;
     int TW = m4ri_tile_words(k, tables);
-    if (w_hi > w_lo && TW > w_hi - w_lo) TW = w_hi - w_lo;
-    const int ny = w_hi > w_lo ? (w_hi - w_lo + TW - 1) / TW : 1;
+    if (TW > w_hi - w_lo) TW = w_hi - w_lo;
+    const int ny = (w_hi - w_lo + TW - 1) / TW;
     const size_t lds = m4ri_lds_bytes(k, tables, TW);
     if (lds > (size_t)M4_LDS_MAX) return hipErrorInvalidValue;
     const int occ = std::max(1, (int)((160 * 1024) / lds));
@@ -305,15 +329,13 @@ hipError_t launch_m4ri_update(uint64_t *A, int64_t stride, int m, int wc, const 
     if (nx < 1) nx = 1;
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)m4ri_update_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           M4_LDS_MAX);
+        e = hipFuncSetAttribute((const void *)m4ri_update_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, M4_LDS_MAX);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(m4ri_update_kernel, dim3(nx, ny), dim3(M4_THREADS), lds, st, A, stride, m, wc,
-                       rk, b, w_lo, w_hi, k, tables, TW, lg_tpr, linv,
-                       reinterpret_cast<const M4riRec *>(rec), Bbuf, bstride);
+    hipLaunchKernelGGL(m4ri_update_kernel, dim3(nx, ny), dim3(M4_THREADS), lds, st, A, stride, m, rk,
+                       b, w_lo, w_hi, k, tables, TW, lg_tpr, rc, cbuf, Bbuf, bstride);
     return hipGetLastError();
 }
 

@@ -162,3 +162,29 @@ def batch_shapes(count: int, seed: int, lo: int = 64, hi: int = 2048,
 
 def batch_matrix(item: BatchItem, stride: int | None = None) -> np.ndarray:
     return planted(item.m, item.n, item.r, item.seed, p=item.p, unit=True, stride=stride)
+
+
+@dataclass(frozen=True)
+class PracticeShape:
+    name: str
+    m: int
+    n: int
+    p: float
+    seed: int
+
+
+# Shapes and densities of the four "matrices from practice" of Table 2
+# (Section 7).  Those matrices are not available; the stand-ins are iid
+# Bernoulli(p) matrices of the same size and density, and match them in nothing
+# else (the originals come with structure and rank deficiency of their own).
+PRACTICE_SHAPES = (
+    PracticeShape("table2_row1", 12307, 13508, 0.076, 25),
+    PracticeShape("table2_row2", 19907, 29323, 0.067, 30),
+    PracticeShape("table2_row3", 29969, 55800, 0.059, 35),
+    PracticeShape("table2_row4", 26075, 26407, 0.185, 40),
+)
+
+
+def practice_matrix(shape: PracticeShape, stride: int | None = None) -> np.ndarray:
+    return random_bernoulli(shape.m, shape.n, shape.p, shape.seed, stride)
+

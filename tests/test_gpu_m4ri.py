@@ -88,6 +88,10 @@ CASES = [
     (1000, 1000, "planted600", 11), (1500, 1200, "p=0.01", 12), (1200, 1800, "p=0.002", 13),
     (2000, 2000, "planted1999", 14), (1300, 3000, "half", 15), (4096, 4096, "half", 1),
     (4096, 4096, "half", 2), (4096, 4096, "p=0.01", 16), (3000, 2000, "planted1700", 17),
+    # many rows and words: the update's grid takes the rows in several chunks per
+    # block, so a row's column tiles run in blocks far apart in time (regression:
+    # its panel word must not change under them)
+    (12307, 13508, "half", 25), (9000, 13508, "p=0.05", 26),
 ]
 
 SCHEDS = [g.Sched(8, 8, 512, g.SCHUR_FP4), g.Sched(4, 1, 512, g.SCHUR_FP4),
