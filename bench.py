@@ -157,7 +157,7 @@ def batched_leg(g, torch, reps: int) -> dict:
     pristine = flat.clone()
     b = g.Batch(mats, [(it.m, it.n) for it in items])
     cm = cmod.CostModel.load()
-    learned = cm.predict(cmod.mix_features(items))
+    learned = cm.predict_dev(cmod.batch_features(b))
     out = {"workload": "4096 matrices, m,n log-uniform [64,2048], p in {0.5,0.1,0.01}, "
                        "planted rank in [min/2,min], seed 7",
            "graph": True}

@@ -91,7 +91,9 @@ void gf2_default_sched(gf2_sched *out);
 /* Non-zero if `s` is a valid schedule. */
 int gf2_sched_valid(const gf2_sched *s);
 
-/* Workspace bytes gf2_pls needs for an m x n matrix under schedule s (NULL: default). */
+/* Workspace bytes gf2_pls needs for an m x n matrix under schedule s.  s == NULL:
+ * enough for any schedule a call without one may run (the default or a learned
+ * choice, see gf2_ctx_set_learned). */
 size_t gf2_pls_workspace_bytes(int64_t m, int64_t n, const gf2_sched *s);
 
 /*
@@ -101,7 +103,8 @@ size_t gf2_pls_workspace_bytes(int64_t m, int64_t n, const gf2_sched *s);
  * > Q[i] hold S[i][.]; for i >= r, columns < r hold L[i][.] and the rest 0.
  * P (m entries), Q (n entries) and *rank (one int32) are device pointers.
  * The result is identical to Gaussian PLS (Appendix A) for every schedule.
- * s == NULL selects the default schedule.
+ * s == NULL: the context's learned choice for (m, n) when one is installed and
+ * covers the shape (gf2_ctx_set_learned), else the default schedule.
  */
 int gf2_pls(gf2_ctx *ctx, gf2_mat A, int32_t *P, int32_t *Q, int32_t *rank,
             const gf2_sched *s, void *ws, size_t ws_bytes, void *stream);
@@ -335,6 +338,39 @@ int gf2_mlp_adam(gf2_ctx *ctx, gf2_mlp net, const float *grad, float *m1, float 
                  float beta1, float beta2, float eps, int step, void *stream);
 int gf2_costmodel_predict(gf2_ctx *ctx, gf2_mlp net, const float *feats, int64_t N,
                           const gf2_sched *table, gf2_sched *out, void *stream);
+
+/*
+ * Features for the cost model computed on the device from the matrices
+ * themselves: feats[i] = (log2 m, log2 n, density, r_est / min(m, n)) of item i
+ * (DEVICE descriptors as for gf2_pls_batched; P and Q are not used).  The
+ * density counts the ones of up to 256 rows spread evenly over the matrix; the
+ * rank estimate r_est is r_hint[i] when r_hint (DEVICE int32[count], nullable)
+ * holds a positive value, else min(m, n).  An invalid item gets zeros.
+ */
+int gf2_features(gf2_ctx *ctx, const gf2_batch_item *items, int64_t count,
+                 const int32_t *r_hint, float *feats, void *stream);
+
+/*
+ * The learned schedule choice for gf2_pls / gf2_pls_noalloc calls with s == NULL.
+ * The network (parameters and its DEVICE schedule table, as for
+ * gf2_costmodel_predict) is evaluated once, now, on the device, for every cell
+ * of a grid of shapes with log2 m and log2 n in [log2_lo, log2_hi] in steps of
+ * 1/2 (at most GF2_LEARNED_MAX_CELLS per side), taking the features of a dense
+ * full-rank input (density 1/2, rank estimate min(m, n)), since a call's
+ * density is not known before it runs.  The argmins are kept in the context;
+ * a call without a schedule takes the cell nearest to its (log2 m, log2 n), and
+ * the default schedule for shapes more than a quarter step outside the grid
+ * (outside the training range).  net.params == NULL removes the choice.
+ * Waits on `stream` (the choice is read back).  The workspace holds
+ * gf2_ctx_set_learned_workspace_bytes() bytes.
+ * gf2_ctx_learned_sched: the schedule a call without one would use for m x n;
+ * returns 1 when it is the learned choice, 0 for the default.
+ */
+#define GF2_LEARNED_MAX_CELLS 64
+size_t gf2_ctx_set_learned_workspace_bytes(void);
+int gf2_ctx_set_learned(gf2_ctx *ctx, gf2_mlp net, const gf2_sched *table, float log2_lo,
+                        float log2_hi, void *ws, size_t ws_bytes, void *stream);
+int gf2_ctx_learned_sched(gf2_ctx *ctx, int64_t m, int64_t n, gf2_sched *out);
 
 /* Workspace bytes gf2_addmul needs for C (m x n) += A (m x k) * B (k x n). */
 size_t gf2_addmul_workspace_bytes(int64_t m, int64_t k, int64_t n);

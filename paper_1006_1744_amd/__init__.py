@@ -140,6 +140,14 @@ def _load():
     L.gf2_mlp_adam.restype = i32
     L.gf2_costmodel_predict.argtypes = [vp, MlpNet, vp, i64, vp, vp, vp]
     L.gf2_costmodel_predict.restype = i32
+    L.gf2_features.argtypes = [vp, vp, i64, vp, vp, vp]
+    L.gf2_features.restype = i32
+    L.gf2_ctx_set_learned_workspace_bytes.argtypes = []
+    L.gf2_ctx_set_learned_workspace_bytes.restype = sz
+    L.gf2_ctx_set_learned.argtypes = [vp, MlpNet, vp, fp, fp, vp, sz, vp]
+    L.gf2_ctx_set_learned.restype = i32
+    L.gf2_ctx_learned_sched.argtypes = [vp, i64, i64, ctypes.POINTER(Sched)]
+    L.gf2_ctx_learned_sched.restype = i32
     L.gf2_addmul_workspace_bytes.argtypes = [i64, i64, i64]
     L.gf2_addmul_workspace_bytes.restype = sz
     L.gf2_addmul.argtypes = [vp, Mat, Mat, Mat, i32, vp, sz, vp]
@@ -439,6 +447,57 @@ def costmodel_predict(params: torch.Tensor, S: int, feats: torch.Tensor, table: 
                                            MlpNet(_f32(params, "params"), S), _f32(feats, "feats"),
                                            N, table.data_ptr(), out.data_ptr(), _stream(stream)))
     return out[:N]
+
+
+def items_of(mats, shapes, device=None) -> torch.Tensor:
+    """Device descriptor array (gf2_batch_item[]) for int64 CUDA matrices (P, Q
+    unset): the argument of gf2_features."""
+    arr = (BatchItem * max(len(mats), 1))()
+    for j, (t, (m, n)) in enumerate(zip(mats, shapes)):
+        if t.dtype != torch.int64 or not t.is_cuda or t.dim() != 2 or not t.is_contiguous():
+            raise ValueError("matrix must be a contiguous 2-D int64 CUDA tensor")
+        arr[j] = BatchItem(t.data_ptr(), m, n, t.shape[1], None, None)
+    dev = mats[0].device if mats else torch.device(device or "cuda")
+    return torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).to(dev)
+
+
+def features(items: torch.Tensor, count: int, r_hint: torch.Tensor | None = None,
+             stream=None) -> torch.Tensor:
+    """Cost-model features of `count` matrices computed on the device from the
+    matrices themselves (gf2_features): float32 CUDA (count, 4)."""
+    out = torch.empty((max(count, 1), 4), dtype=torch.float32, device=items.device)
+    _check(get_lib().gf2_features(ctx(items.device.index), items.data_ptr(), count,
+                                  r_hint.data_ptr() if r_hint is not None else None,
+                                  out.data_ptr(), _stream(stream)))
+    return out[:count]
+
+
+def set_learned(params: torch.Tensor | None, S: int = 0, table: torch.Tensor | None = None,
+                log2_lo: float = 6.0, log2_hi: float = 16.0, device=None, stream=None):
+    """Install (or with params None remove) the learned choice gf2_pls uses when
+    it is given no schedule (gf2_ctx_set_learned).  Waits on the stream."""
+    dev = torch.cuda.current_device() if device is None else device
+    L = get_lib()
+    if params is None:
+        _check(L.gf2_ctx_set_learned(ctx(dev), MlpNet(None, 0), None, 0.0, 0.0, None, 0,
+                                     _stream(stream)))
+        return
+    if table is None or table.dtype != torch.int32 or tuple(table.shape) != (S, 4):
+        raise ValueError("table must be an int32 (S, 4) tensor")
+    ws = workspace(int(L.gf2_ctx_set_learned_workspace_bytes()), params.device)
+    _check(L.gf2_ctx_set_learned(ctx(dev), MlpNet(_f32(params, "params"), S), table.data_ptr(),
+                                 float(log2_lo), float(log2_hi), ws.data_ptr(), ws.numel(),
+                                 _stream(stream)))
+
+
+def learned_sched(m: int, n: int, device=None):
+    """(schedule a call without one would use for m x n, True if it is learned)."""
+    dev = torch.cuda.current_device() if device is None else device
+    out = Sched()
+    rc = get_lib().gf2_ctx_learned_sched(ctx(dev), m, n, ctypes.byref(out))
+    if rc < 0:
+        _check(rc)
+    return Sched(*out.astuple()), rc == 1
 
 
 def pls_unpack(A_pls: torch.Tensor, m: int, n: int, Q: torch.Tensor, rank: torch.Tensor,

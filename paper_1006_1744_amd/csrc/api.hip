@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -41,6 +42,11 @@ struct gf2_ctx {
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
     void *scratch = nullptr;   // this device's copy of `scratch` (device address)
+    // learned schedule choice for calls without a schedule: one schedule per
+    // cell of a half-log2 grid of (m, n) over [l_lo, l_hi]^2, row-major by m
+    std::vector<gf2_sched> learned;
+    float l_lo = 0.f, l_hi = -1.f;
+    int l_cells = 0;
 };
 
 // Scratch memory of gf2_pls_noalloc: one copy per device, held until the process
@@ -351,6 +357,23 @@ int check_mat(const gf2_mat &A) {
     return GF2_OK;
 }
 
+// The schedule of a call without one: the learned cell of (m, n) when the
+// context holds a learned choice covering it, else the default.
+gf2_sched choose_sched(const gf2_ctx *ctx, int64_t m, int64_t n, bool *learned = nullptr) {
+    if (learned) *learned = false;
+    if (!ctx || ctx->l_cells <= 0 || m <= 0 || n <= 0) return default_sched();
+    const double lm = std::log2((double)m), ln = std::log2((double)n);
+    if (lm < ctx->l_lo - 0.25 || lm > ctx->l_hi + 0.25 || ln < ctx->l_lo - 0.25 ||
+        ln > ctx->l_hi + 0.25)
+        return default_sched();
+    const int im = std::min(ctx->l_cells - 1, std::max(0, (int)std::lround((lm - ctx->l_lo) * 2.0)));
+    const int in = std::min(ctx->l_cells - 1, std::max(0, (int)std::lround((ln - ctx->l_lo) * 2.0)));
+    const gf2_sched c = ctx->learned[(size_t)im * ctx->l_cells + in];
+    if (!sched_ok(&c)) return default_sched();
+    if (learned) *learned = true;
+    return c;
+}
+
 // Launches the recursion for A with its workspace at `base` (layout L).
 int pls_run(gf2_ctx *ctx, const gf2_mat &A, int32_t *P, int32_t *Q, int32_t *rank,
             const gf2_sched &ss, const PlsLayout &L, char *base, hipStream_t st) {
@@ -500,9 +523,19 @@ int gf2_sched_valid(const gf2_sched *s) { return sched_ok(s) ? 1 : 0; }
 
 size_t gf2_pls_workspace_bytes(int64_t m, int64_t n, const gf2_sched *s) {
     if (m < 0 || n < 0 || m > kMaxDim || n > kMaxDim) return 0;
-    gf2_sched ss = s ? *s : default_sched();
-    if (!sched_ok(&ss)) return 0;
-    return pls_layout(m, n, ss).total;
+    if (s) {
+        if (!sched_ok(s)) return 0;
+        return pls_layout(m, n, *s).total;
+    }
+    // no schedule: enough for any a context may choose (the cutoff alone sets
+    // the layout; k, tables and the product variant do not)
+    size_t need = pls_layout(m, n, default_sched()).total;
+    for (int c = 256; c <= 4096; c *= 2) {
+        gf2_sched t = default_sched();
+        t.cutoff = c;
+        need = std::max(need, pls_layout(m, n, t).total);
+    }
+    return need;
 }
 
 int gf2_pls(gf2_ctx *ctx, gf2_mat A, int32_t *P, int32_t *Q, int32_t *rank, const gf2_sched *s,
@@ -510,7 +543,7 @@ int gf2_pls(gf2_ctx *ctx, gf2_mat A, int32_t *P, int32_t *Q, int32_t *rank, cons
     if (!ctx) return GF2_E_ARG;
     int rc = check_mat(A);
     if (rc != GF2_OK) return rc;
-    gf2_sched ss = s ? *s : default_sched();
+    gf2_sched ss = s ? *s : choose_sched(ctx, A.m, A.n);
     if (!sched_ok(&ss)) return GF2_E_ARG;
     if (!rank || (A.m > 0 && !P) || (A.n > 0 && !Q)) return GF2_E_ARG;
     PlsLayout L = pls_layout(A.m, A.n, ss);
@@ -524,7 +557,7 @@ int gf2_pls_noalloc(gf2_ctx *ctx, gf2_mat A, int32_t *P, int32_t *Q, int32_t *ra
     if (!ctx) return GF2_E_ARG;
     int rc = check_mat(A);
     if (rc != GF2_OK) return rc;
-    gf2_sched ss = s ? *s : default_sched();
+    gf2_sched ss = s ? *s : choose_sched(ctx, A.m, A.n);
     if (!sched_ok(&ss)) return GF2_E_ARG;
     if (!rank || (A.m > 0 && !P) || (A.n > 0 && !Q)) return GF2_E_ARG;
     PlsLayout L = pls_layout(A.m, A.n, ss);
@@ -534,6 +567,61 @@ int gf2_pls_noalloc(gf2_ctx *ctx, gf2_mat A, int32_t *P, int32_t *Q, int32_t *ra
 }
 
 size_t gf2_pls_noalloc_max_bytes(void) { return (size_t)GF2_NOALLOC_SCRATCH_BYTES; }
+
+size_t gf2_ctx_set_learned_workspace_bytes(void) {
+    const size_t cells = (size_t)GF2_LEARNED_MAX_CELLS * GF2_LEARNED_MAX_CELLS;
+    return align_up(cells * 4 * sizeof(float)) + align_up(cells * sizeof(gf2_sched));
+}
+
+int gf2_ctx_set_learned(gf2_ctx *ctx, gf2_mlp net, const gf2_sched *table, float log2_lo,
+                        float log2_hi, void *ws, size_t ws_bytes, void *stream) {
+    if (!ctx) return GF2_E_ARG;
+    if (!net.params) {   // back to the default for every call without a schedule
+        ctx->learned.clear();
+        ctx->l_cells = 0;
+        return GF2_OK;
+    }
+    if (net.S < 1 || net.S > GF2_MLP_MAX_S || !table) return GF2_E_ARG;
+    if (!(log2_lo >= 0.f && log2_hi >= log2_lo && log2_hi <= 30.f)) return GF2_E_ARG;
+    const int cells = (int)std::lround((log2_hi - log2_lo) * 2.0f) + 1;
+    if (cells > GF2_LEARNED_MAX_CELLS) return GF2_E_ARG;
+    if (!ws || ws_bytes < gf2_ctx_set_learned_workspace_bytes()) return GF2_E_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0) return GF2_E_ALIGN;
+    if (hipSetDevice(ctx->device) != hipSuccess) return GF2_E_HIP;
+    const int N = cells * cells;
+    std::vector<float> f((size_t)N * 4);
+    for (int a = 0; a < cells; a++)
+        for (int b = 0; b < cells; b++) {
+            float *r = &f[((size_t)a * cells + b) * 4];
+            r[0] = log2_lo + 0.5f * a;
+            r[1] = log2_lo + 0.5f * b;
+            r[2] = 0.5f;   // a dense input: the density of a call is not known up front
+            r[3] = 1.0f;   // full rank assumed for the same reason
+        }
+    const size_t cells_max = (size_t)GF2_LEARNED_MAX_CELLS * GF2_LEARNED_MAX_CELLS;
+    float *fd = (float *)ws;
+    gf2_sched *od = (gf2_sched *)((char *)ws + align_up(cells_max * 4 * sizeof(float)));
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<gf2_sched> out((size_t)N);
+    GF2_TRY(hipMemcpyAsync(fd, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    GF2_TRY(launch_costmodel_predict(net.params, net.S, fd, N, table, od, st));
+    GF2_TRY(hipMemcpyAsync(out.data(), od, out.size() * sizeof(gf2_sched), hipMemcpyDeviceToHost, st));
+    GF2_TRY(hipStreamSynchronize(st));
+    for (const gf2_sched &c : out)
+        if (!sched_ok(&c)) return GF2_E_ARG;   // a table row that is not a schedule
+    ctx->learned = std::move(out);
+    ctx->l_lo = log2_lo;
+    ctx->l_hi = log2_lo + 0.5f * (cells - 1);
+    ctx->l_cells = cells;
+    return GF2_OK;
+}
+
+int gf2_ctx_learned_sched(gf2_ctx *ctx, int64_t m, int64_t n, gf2_sched *out) {
+    if (!ctx || !out) return GF2_E_ARG;
+    bool learned = false;
+    *out = choose_sched(ctx, m, n, &learned);
+    return learned ? 1 : 0;
+}
 
 int gf2_pls_unpack(gf2_ctx *ctx, gf2_mat A_pls, const int32_t *Q, const int32_t *rank,
                    gf2_mat L_out, gf2_mat S_out, void *stream) {

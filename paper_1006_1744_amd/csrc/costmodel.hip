@@ -17,6 +17,8 @@ hipError_t launch_mlp_adam(float *params, const float *grad, float *m1, float *m
                            float beta1, float beta2, float eps, int step, hipStream_t st);
 hipError_t launch_costmodel_predict(const float *params, int S, const float *feats, int N,
                                     const gf2_sched *table, gf2_sched *out, hipStream_t st);
+hipError_t launch_features(const gf2_batch_item *items, int count, const int32_t *r_hint,
+                           float *feats, hipStream_t st);
 }  // namespace gf2
 
 namespace {
@@ -72,6 +74,15 @@ int gf2_costmodel_predict(gf2_ctx *ctx, gf2_mlp net, const float *feats, int64_t
     if (!ctx || !net_ok(net) || !n_ok(N) || (N > 0 && (!feats || !table || !out))) return GF2_E_ARG;
     return hip_rc(gf2::launch_costmodel_predict(net.params, net.S, feats, (int)N, table, out,
                                                 (hipStream_t)stream));
+}
+
+int gf2_features(gf2_ctx *ctx, const gf2_batch_item *items, int64_t count, const int32_t *r_hint,
+                 float *feats, void *stream) {
+    if (!ctx || count < 0 || count > ((int64_t)1 << 30)) return GF2_E_ARG;
+    if (count == 0) return GF2_OK;
+    if (!items || !feats) return GF2_E_ARG;
+    if (((uintptr_t)items & 7) != 0 || ((uintptr_t)feats & 3) != 0) return GF2_E_ALIGN;
+    return hip_rc(gf2::launch_features(items, (int)count, r_hint, feats, (hipStream_t)stream));
 }
 
 }  // extern "C"

@@ -191,6 +191,11 @@ hipError_t launch_gather_cols(const uint64_t *X, int64_t sx, int rows, int nw, c
 hipError_t launch_mp_finish(int32_t *Q, int32_t *rank, int32_t *ext, const int32_t *Q2,
                             const int32_t *rank2, int R, int c0, int n, hipStream_t st);
 
+// Learned cost model (k_mlp.hip): per problem the table row of the smallest
+// predicted log time.
+hipError_t launch_costmodel_predict(const float *params, int S, const float *feats, int N,
+                                    const gf2_sched *table, gf2_sched *out, hipStream_t st);
+
 // Batched PLS (k_batch.hip): queue order, then one persistent launch of `grid`
 // blocks.  ws holds batch_ws_bytes(count) bytes.
 size_t batch_ws_bytes(int64_t count);

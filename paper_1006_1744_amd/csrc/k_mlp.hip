@@ -278,8 +278,57 @@ __global__ __launch_bounds__(MLP_THREADS) void costmodel_predict_kernel(
     }
 }
 
+// Features of problem i from its matrix: (log2 m, log2 n, density, rank
+// estimate / min(m, n)); the density counts the ones of up to 256 rows spread
+// evenly over the matrix (all of its words), the rank estimate is the caller's
+// hint when positive, else min(m, n).  One block per problem.
+__global__ __launch_bounds__(256) void features_kernel(const gf2_batch_item *items, int count,
+                                                       const int32_t *r_hint, float *feats) {
+    __shared__ unsigned long long s_cnt;
+    const int i = blockIdx.x;
+    if (i >= count) return;
+    const gf2_batch_item it = items[i];
+    const int64_t m = it.m, n = it.n;
+    float *f = feats + 4 * (int64_t)i;
+    if (m <= 0 || n <= 0 || !it.words || it.stride < (n + 63) / 64) {
+        if (threadIdx.x < 4) f[threadIdx.x] = 0.f;
+        return;
+    }
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    const int S = (int)min<int64_t>(m, 256);
+    const int64_t nw = (n + 63) / 64;
+    if ((int)threadIdx.x < S) {
+        const int64_t row = ((int64_t)threadIdx.x * m) / S;
+        const uint64_t *pr = it.words + row * it.stride;
+        unsigned long long c = 0;
+        for (int64_t w = 0; w < nw; w++) {
+            uint64_t x = pr[w];
+            if (w == nw - 1 && (n & 63)) x &= (1ull << (n & 63)) - 1;
+            c += __popcll(x);
+        }
+        atomicAdd(&s_cnt, c);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double mn = (double)min(m, n);
+        const int hint = r_hint ? r_hint[i] : 0;
+        f[0] = (float)log2((double)m);
+        f[1] = (float)log2((double)n);
+        f[2] = (float)((double)s_cnt / ((double)S * (double)n));
+        f[3] = (float)((hint > 0 ? min((double)hint, mn) : mn) / mn);
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 int64_t mlp_param_count(int S) { return mlp_params(S); }
+
+hipError_t launch_features(const gf2_batch_item *items, int count, const int32_t *r_hint,
+                           float *feats, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(features_kernel, dim3(count), dim3(256), 0, st, items, count, r_hint, feats);
+    return hipGetLastError();
+}
 size_t mlp_lds_bytes(int S) { return mlp_lds_floats(S) * sizeof(float); }
 int mlp_blocks(int64_t N) { return (int)((N + MLP_BS - 1) / MLP_BS); }
 
