@@ -262,15 +262,19 @@ struct PlsDriver {
         const int64_t sb = buffered ? nwd : stride;
         const int blk_lo = buffered ? wb : 0, blk_hi = buffered ? wb + nwd : (int)stride;
         if (buffered && !dry) chk(launch_copy_rows(pbuf, nwd, 0, A, stride, wb, nwd, rk, wb, m, st));
+        // search(0), then per panel: its post pass, and the update of the block's
+        // remaining words fused with the next panel's search
+        if (!dry) chk(launch_leaf_search(Ab, sb, m, n, wb, rk, wb, P, Q, info, st));
         for (int p = 0; p < nwd; p++) {
             const int wc = wb + p;
             const bool upd = p + 1 < nwd;
-            if (!dry)
-                chk(launch_leaf(A, stride, Ab, sb, blk_lo, blk_hi, m, n, wc, rk, wc, P, Q, info,
-                                upd ? Bbuf : nullptr, bstride, wc + 1, wb + nwd, linv_store, st));
-            if (upd && !dry)
-                chk(launch_table_update(Ab, sb, m, wc, rk, wc, wc + 1, wb + nwd, s.k, s.tables, linv,
-                                        Bbuf, bstride, cus, st));
+            if (dry) continue;
+            chk(launch_panel_post(A, stride, Ab, sb, blk_lo, blk_hi, m, n, wc, rk, wc, info,
+                                  upd ? Bbuf : nullptr, bstride, wc + 1, wb + nwd, linv_store,
+                                  p > 0, st));
+            if (upd)
+                chk(launch_table_update_search(Ab, sb, m, n, wc, rk, wc, wc + 1, wb + nwd, s.k,
+                                               s.tables, linv, Bbuf, bstride, P, Q, info, cus, st));
         }
         if (!dry) {
             if (buffered)

@@ -65,6 +65,16 @@ hipError_t launch_leaf(uint64_t *A, int64_t stride, uint64_t *Ab, int64_t sb, in
                        int blk_hi, int m, int n, int wc, int32_t *rk, int b, int32_t *P, int32_t *Q,
                        int32_t *info, uint64_t *Bbuf, int64_t bstride, int bw_lo, int bw_hi,
                        uint64_t *linv_store, hipStream_t st);
+// The two halves of launch_leaf: the search (one block; P, Q, rk[b + 1], *info)
+// and the pass after it (final pass, moves, staging, L^{-1}); lazy: the search
+// was launch_table_update_search's, and the final pass also adds the previous
+// panel's update (info->unext) to the rows the search did not reach.
+hipError_t launch_leaf_search(uint64_t *Ab, int64_t sb, int m, int n, int wc, int32_t *rk, int b,
+                              int32_t *P, int32_t *Q, int32_t *info, hipStream_t st);
+hipError_t launch_panel_post(uint64_t *A, int64_t stride, uint64_t *Ab, int64_t sb, int blk_lo,
+                             int blk_hi, int m, int n, int wc, int32_t *rk, int b, int32_t *info,
+                             uint64_t *Bbuf, int64_t bstride, int bw_lo, int bw_hi,
+                             uint64_t *linv_store, bool lazy, hipStream_t st);
 size_t panel_info_bytes();
 size_t panel_info_linv_offset();
 
@@ -90,6 +100,16 @@ hipError_t launch_table_update(uint64_t *A, int64_t stride, int m, int wc, const
                                int b, int w_lo, int w_hi, int k, int tables, const uint64_t *linv,
                                const uint64_t *Bbuf, int64_t bstride, int target_blocks,
                                hipStream_t st);
+// The same update (w_hi > w_lo = wc + 1) fused with the search of the next panel
+// (word wc + 1, rows [rk[b + 1], m); writes rk[b + 2], P, Q and *info as
+// launch_leaf_search does).  The rows the search does not reach (offsets >= F of
+// *info) are left without the update of word wc + 1: the post pass of panel
+// wc + 1 must run with lazy = true.
+hipError_t launch_table_update_search(uint64_t *A, int64_t stride, int m, int n, int wc, int32_t *rk,
+                                      int b, int w_lo, int w_hi, int k, int tables,
+                                      const uint64_t *linv, const uint64_t *Bbuf, int64_t bstride,
+                                      int32_t *P, int32_t *Q, int32_t *info, int target_blocks,
+                                      hipStream_t st);
 
 // Move the second block's L columns next to the first block's (Section 5,
 // final "compress L"): node at column c0 (multiple of 64), split n0 columns,

@@ -43,7 +43,20 @@ struct PanelInfo {
     uint64_t u[64];  // pivot rows' panel words when chosen (reduced by earlier pivots)
     uint64_t linv[64];  // rows of L^{-1} for the panel's r x r unit lower triangle
     int32_t moved[kMovedInts];
+    // When the search ran fused with the update after the previous panel: that
+    // panel's pivot rows' words on this panel's column (U = L^{-1} B there), zero
+    // past its rank.  Rows the search did not reach (offsets >= F) still lack
+    // their part of that update, x += l U with l their previous-panel word.
+    uint64_t unext[64];
 };
+
+// x + l U on one word: 8 lookups in the 8 tables of 256 combinations of U's rows
+// (T[g * 256 + e], build_tables_8x8), l the row's multipliers.
+__device__ inline uint64_t add_lu(uint64_t x, uint64_t l, const uint64_t *T) {
+#pragma unroll
+    for (int g = 0; g < 8; g++) x ^= T[g * 256 + (int)((l >> (8 * g)) & 255)];
+    return x;
+}
 
 // Build tables for pivots [ta, tb) (consecutive columns q[ta], q[ta]+1, ...):
 // group g holds pivots ta+8g .. ; entry [key] added to a row whose group bits
@@ -112,7 +125,7 @@ __device__ inline int writelane32(int v, int l, int old) {
 }
 
 
-// LDS of one search (all threads of a 256-thread block take part).
+// LDS of one search (every thread of the block takes part).
 struct SearchLds {
     uint64_t sU[64];
     int32_t sQ[64];
@@ -147,9 +160,16 @@ __device__ inline uint64_t panel_linv_row(uint64_t urow, int qv, int ru, int lan
 // the pivot slots R + t, the window rows' and scanned rows' panel words, and
 // *info (r, F, pa, compress, q, u, moved), and, when want_linv, L^{-1} to
 // info->linv and to linv_out (64 words) when given.  Returns r (in every thread).
+// Every one of the block's NT threads calls it.
+// LAZY: the previous panel's update has not reached this panel's word yet; a row
+// receives it (add_lu with tables TU and the row's word wc - 1) when the search
+// first loads it, i.e. at offsets >= F, so rows the search never reaches keep
+// lacking it (info->unext, the post pass).
+template <int NT = LEAF_THREADS, bool LAZY = false>
 __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, int wc, int R,
                                    int32_t *P, int32_t *Q, PanelInfo *info, SearchLds &S,
-                                   uint64_t *linv_out = nullptr, bool want_linv = true) {
+                                   uint64_t *linv_out = nullptr, bool want_linv = true,
+                                   const uint64_t *TU = nullptr) {
     uint64_t *sU = S.sU;
     int32_t *sQ = S.sQ;
     int32_t *sPrel = S.sPrel;
@@ -183,7 +203,7 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
         if (mrem <= 0 || c >= nc || t >= mrem) break;
         if (epochs > 0) simple = false;
         const bool need_tab = F < mrem && t > pa && (tl != pa || th != t);
-        if (need_tab) build_tables<LEAF_THREADS>(sU, sQ, pa, t, sT, tid);
+        if (need_tab) build_tables<NT>(sU, sQ, pa, t, sT, tid);
         __syncthreads();
         if (need_tab && tid == 0) { s_tab_lo = pa; s_tab_hi = t; }
         const int ts = t;
@@ -196,6 +216,13 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
             const int o0 = ts + lane, o1 = ts + 64 + lane;
             uint64_t x0 = o0 < mrem ? col[(int64_t)o0 * stride] : 0ull;
             uint64_t x1 = o1 < mrem ? col[(int64_t)o1 * stride] : 0ull;
+            if constexpr (LAZY) {
+                const bool n0 = o0 < mrem && o0 >= F, n1 = o1 < mrem && o1 >= F;
+                const uint64_t l0 = n0 ? col[(int64_t)o0 * stride - 1] : 0ull;
+                const uint64_t l1 = n1 ? col[(int64_t)o1 * stride - 1] : 0ull;
+                if (n0) x0 = add_lu(x0, l0, TU);
+                if (n1) x1 = add_lu(x1, l1, TU);
+            }
             if (t > pa) {
                 if (o0 < mrem && o0 >= F) x0 = apply_tables(x0, sQ, pa, t, sT);
                 if (o1 < mrem && o1 >= F) x1 = apply_tables(x1, sQ, pa, t, sT);
@@ -312,9 +339,9 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
         // Rows between the window and an older frontier miss this epoch's pivots.
         const int wend = min(ts + LEAF_W, mrem);
         if (t1 > ts && F > wend) {
-            build_tables<LEAF_THREADS>(sU, sQ, ts, t1, sE, tid);
+            build_tables<NT>(sU, sQ, ts, t1, sE, tid);
             __syncthreads();
-            for (int o = wend + tid; o < F; o += LEAF_THREADS)
+            for (int o = wend + tid; o < F; o += NT)
                 col[(int64_t)o * stride] = apply_tables(col[(int64_t)o * stride], sQ, ts, t1, sE);
             __syncthreads();
         }
@@ -326,22 +353,23 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
         const int F2 = s_F, pa2 = s_pa, tl2 = s_tab_lo, th2 = s_tab_hi;
         __syncthreads();
         const bool need2 = F2 < mrem && t1 > pa2 && (tl2 != pa2 || th2 != t1);
-        if (need2) build_tables<LEAF_THREADS>(sU, sQ, pa2, t1, sT, tid);
+        if (need2) build_tables<NT>(sU, sQ, pa2, t1, sT, tid);
         if (tid == 0) s_far = NOHIT;
         __syncthreads();
         if (need2 && tid == 0) { s_tab_lo = pa2; s_tab_hi = t1; }
         int scan_end = wend;
-        for (int base = wend; base < mrem; base += LEAF_THREADS) {
+        for (int base = wend; base < mrem; base += NT) {
             const int o = base + tid;
             if (o < mrem) {
                 uint64_t v = col[(int64_t)o * stride];
-                if (o >= F2 && t1 > pa2) {
-                    v = apply_tables(v, sQ, pa2, t1, sT);
+                if (o >= F2 && (LAZY || t1 > pa2)) {
+                    if constexpr (LAZY) v = add_lu(v, col[(int64_t)o * stride - 1], TU);
+                    if (t1 > pa2) v = apply_tables(v, sQ, pa2, t1, sT);
                     col[(int64_t)o * stride] = v;
                 }
                 if ((v >> c1) & 1) atomicMin(&s_far, o);
             }
-            scan_end = min(base + LEAF_THREADS, mrem);
+            scan_end = min(base + NT, mrem);
             __syncthreads();
             const bool hit = s_far != NOHIT;
             __syncthreads();
@@ -371,7 +399,7 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
             // rows after f up to the new frontier may hold a one in column c1
             const uint64_t pw = sU[t1];
             const uint64_t above = c1 == 63 ? 0ull : (~0ull << (c1 + 1));
-            for (int o = f + 1 + tid; o < F3; o += LEAF_THREADS) {
+            for (int o = f + 1 + tid; o < F3; o += NT) {
                 uint64_t v = col[(int64_t)o * stride];
                 if ((v >> c1) & 1) col[(int64_t)o * stride] = v ^ (pw & above);
             }

@@ -18,9 +18,11 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
 
 // Final pass over the panel (blocks [0, nfin)) and the other word columns of
 // the moved rows (blocks [nfin, ...)), which touch disjoint words.
-//  * final pass: rows >= F receive the pending pivots [pa, r) through their
-//    tables, and every row gets the panel's "compress L" column swaps; each
-//    thread holds POST_ROWS rows so that their loads are in flight together.
+//  * final pass: rows >= F receive the previous panel's update of this word
+//    when the search ran fused with it (lazy: l U, U = info->unext, l the row's
+//    previous word), then the pending pivots [pa, r) through their tables, and
+//    every row gets the panel's "compress L" column swaps; a thread's first
+//    row is loaded before the tables are built.
 //  * moves: the (destination, source) list goes to LDS once; a block copies
 //    SWAP_W word columns of every moved row through LDS (all reads, one
 //    barrier, all writes), and stages the pivot rows' words on [bw_lo, bw_hi)
@@ -28,14 +30,16 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
 //  * the last block computes the panel's L^{-1} (info->linv and the per-panel
 //    store) from the pivot words and columns the search recorded.
 constexpr int POST_THREADS = 1024;
-constexpr int POST_ROWS = 1;
 constexpr int SWAP_W = 16;
 
+template <bool LAZY>
 __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
     uint64_t *A, int64_t stride, uint64_t *Ab, int64_t sb, int blk_lo, int blk_hi, int m, int wc,
     int nwords, const int32_t *rk, int b, PanelInfo *info, int nfin, uint64_t *Bbuf,
     int64_t bstride, int bw_lo, int bw_hi, uint64_t *linv_store) {
     __shared__ uint64_t sT[8][256];
+    __shared__ uint64_t sTU[8 * 256];   // combinations of info->unext (lazy)
+    __shared__ uint64_t sUn[64];
     __shared__ uint64_t sU[64];
     __shared__ int32_t sQ[64];
     __shared__ uint64_t stage[kMaxMoved * SWAP_W];
@@ -57,42 +61,57 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
     }
     if ((int)blockIdx.x < nfin) {
         const bool pend = (F < mrem) && (r > pa);
-        if (!pend && !cmp) return;
-        if (tid < 64) {
-            sU[tid] = info->u[tid];
-            sQ[tid] = info->q[tid];
-        }
-        __syncthreads();
-        if (pend) build_tables<POST_THREADS>(sU, sQ, pa, r, sT, tid);
-        __syncthreads();
+        const bool lazy = LAZY && F < mrem;   // rows >= F lack the previous update
+        if (!pend && !cmp && !lazy) return;
         uint64_t *col = Ab + (int64_t)R * sb + wc;   // the panel word lies in the block
-        const int step = nfin * POST_THREADS * POST_ROWS;
-        for (int base = blockIdx.x * POST_THREADS * POST_ROWS; base < mrem; base += step) {
-            uint64_t v[POST_ROWS];
-#pragma unroll
-            for (int u = 0; u < POST_ROWS; u++) {
-                const int o = base + u * POST_THREADS + tid;
-                v[u] = o < mrem ? col[(int64_t)o * sb] : 0ull;
+        const int step = nfin * POST_THREADS;
+        // the first row's words are loaded before the tables are built and stay in
+        // flight across the barriers (they wait for LDS traffic only)
+        // (the panel record's words are requested first, so that storing them to
+        // LDS waits for them alone)
+        const bool wave0 = __builtin_amdgcn_readfirstlane(tid >> 6) == 0;
+        const int l64 = tid & 63;
+        uint64_t iu = 0, iun = 0;
+        int iq = 0;
+        if (wave0) {
+            iu = info->u[l64];
+            iq = info->q[l64];
+            if (LAZY) iun = info->unext[l64];
+        }
+        // (addresses clamped to a valid row: the loads are unconditional)
+        int o = blockIdx.x * POST_THREADS + tid;
+        const int64_t oc = (int64_t)min(o, mrem - 1) * sb;
+        uint64_t v = col[oc];
+        uint64_t lp = LAZY ? col[oc - 1] : 0ull;   // word wc - 1 lies in the block when LAZY
+        if (wave0) {
+            sU[l64] = iu;
+            sQ[l64] = iq;
+            sUn[l64] = iun;
+        }
+        block_sync<true>();
+        if (pend) build_tables<POST_THREADS>(sU, sQ, pa, r, sT, tid);
+        if (lazy) build_tables_8x8<POST_THREADS, true>(sUn, sTU, tid);
+        block_sync<true>();
+        for (; o < mrem; o += step) {
+            if (o >= (int)(blockIdx.x + nfin) * POST_THREADS) {
+                v = col[(int64_t)o * sb];
+                lp = LAZY ? col[(int64_t)o * sb - 1] : 0ull;
             }
-#pragma unroll
-            for (int u = 0; u < POST_ROWS; u++) {
-                const int o = base + u * POST_THREADS + tid;
-                if (o >= mrem) continue;
-                uint64_t w = v[u];
-                if (pend && o >= F) w = apply_tables(w, sQ, pa, r, sT);
-                if (cmp) {
-                    // compress L: swap panel columns s and q[s] in rows o >= s
-                    const int lim = min(o + 1, r);
-                    for (int s2 = 0; s2 < lim; s2++) {
-                        const int qs = sQ[s2];
-                        if (qs != s2) {
-                            const uint64_t d = ((w >> s2) ^ (w >> qs)) & 1ull;
-                            w ^= (d << s2) | (d << qs);
-                        }
+            uint64_t w = v;
+            if (lazy && o >= F) w = add_lu(w, lp, sTU);
+            if (pend && o >= F) w = apply_tables(w, sQ, pa, r, sT);
+            if (cmp) {
+                // compress L: swap panel columns s and q[s] in rows o >= s
+                const int lim = min(o + 1, r);
+                for (int s2 = 0; s2 < lim; s2++) {
+                    const int qs = sQ[s2];
+                    if (qs != s2) {
+                        const uint64_t d = ((w >> s2) ^ (w >> qs)) & 1ull;
+                        w ^= (d << s2) | (d << qs);
                     }
                 }
-                if (w != v[u]) col[(int64_t)o * sb] = w;
             }
+            if (w != v) col[(int64_t)o * sb] = w;
         }
         return;
     }
@@ -133,24 +152,43 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
     }
 }
 
+hipError_t launch_leaf_search(uint64_t *Ab, int64_t sb, int m, int n, int wc, int32_t *rk, int b,
+                              int32_t *P, int32_t *Q, int32_t *infobuf, hipStream_t st) {
+    PanelInfo *info = reinterpret_cast<PanelInfo *>(infobuf);
+    hipLaunchKernelGGL(leaf_search_kernel, dim3(1), dim3(LEAF_THREADS), 0, st, Ab, sb, m, n, wc, rk,
+                       b, P, Q, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_panel_post(uint64_t *A, int64_t stride, uint64_t *Ab, int64_t sb, int blk_lo,
+                             int blk_hi, int m, int n, int wc, int32_t *rk, int b, int32_t *infobuf,
+                             uint64_t *Bbuf, int64_t bstride, int bw_lo, int bw_hi,
+                             uint64_t *linv_store, bool lazy, hipStream_t st) {
+    PanelInfo *info = reinterpret_cast<PanelInfo *>(infobuf);
+    int nwords = (n + 63) / 64;
+    int nfin = (m + POST_THREADS - 1) / POST_THREADS;
+    if (nfin > 256) nfin = 256;
+    if (nfin < 1) nfin = 1;
+    int nswap = (nwords + SWAP_W - 1) / SWAP_W;
+    if (lazy)
+        hipLaunchKernelGGL(panel_post_kernel<true>, dim3(nfin + nswap + 1), dim3(POST_THREADS), 0, st,
+                           A, stride, Ab, sb, blk_lo, blk_hi, m, wc, nwords, rk, b, info, nfin, Bbuf,
+                           bstride, bw_lo, bw_hi, linv_store);
+    else
+        hipLaunchKernelGGL(panel_post_kernel<false>, dim3(nfin + nswap + 1), dim3(POST_THREADS), 0, st,
+                           A, stride, Ab, sb, blk_lo, blk_hi, m, wc, nwords, rk, b, info, nfin, Bbuf,
+                           bstride, bw_lo, bw_hi, linv_store);
+    return hipGetLastError();
+}
+
 hipError_t launch_leaf(uint64_t *A, int64_t stride, uint64_t *Ab, int64_t sb, int blk_lo,
                        int blk_hi, int m, int n, int wc, int32_t *rk, int b, int32_t *P, int32_t *Q,
                        int32_t *infobuf, uint64_t *Bbuf, int64_t bstride, int bw_lo, int bw_hi,
                        uint64_t *linv_store, hipStream_t st) {
-    PanelInfo *info = reinterpret_cast<PanelInfo *>(infobuf);
-    hipLaunchKernelGGL(leaf_search_kernel, dim3(1), dim3(LEAF_THREADS), 0, st, Ab, sb, m, n, wc, rk,
-                       b, P, Q, info);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_leaf_search(Ab, sb, m, n, wc, rk, b, P, Q, infobuf, st);
     if (e != hipSuccess) return e;
-    int nwords = (n + 63) / 64;
-    int nfin = (m + POST_THREADS * POST_ROWS - 1) / (POST_THREADS * POST_ROWS);
-    if (nfin > 256) nfin = 256;
-    if (nfin < 1) nfin = 1;
-    int nswap = (nwords + SWAP_W - 1) / SWAP_W;
-    hipLaunchKernelGGL(panel_post_kernel, dim3(nfin + nswap + 1), dim3(POST_THREADS), 0, st, A,
-                       stride, Ab, sb, blk_lo, blk_hi, m, wc, nwords, rk, b, info, nfin, Bbuf, bstride,
-                       bw_lo, bw_hi, linv_store);
-    return hipGetLastError();
+    return launch_panel_post(A, stride, Ab, sb, blk_lo, blk_hi, m, n, wc, rk, b, infobuf, Bbuf,
+                             bstride, bw_lo, bw_hi, linv_store, false, st);
 }
 
 size_t panel_info_bytes() { return sizeof(PanelInfo); }

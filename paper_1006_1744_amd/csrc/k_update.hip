@@ -17,6 +17,7 @@
 
 #include "gf2_device.h"
 #include "gf2_internal.h"
+#include "gf2_panel.h"
 
 namespace gf2 {
 
@@ -268,11 +269,14 @@ size_t table_update_lds_bytes(int k, int tables, int TW) {
     return (size_t)(8 * 256 + 64 + 2 * 64 * TW + tables * (1 << k) * TW) * 8;
 }
 
-__global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
-    uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk, int b, int w_lo, int w_hi,
-    int k, int tables, int TW, int lg_tpr, const uint64_t *linv, const uint64_t *Bbuf,
-    int64_t bstride) {
-    extern __shared__ uint64_t tu_lds[];
+// One block's share of the update: target words [w0, w0 + tw_n) (its tile, TW
+// words wide in LDS), rows taken by block bx of the tile's nbx blocks.  Every
+// thread of the block calls it.
+__device__ inline void table_update_tile(uint64_t *A, int64_t stride, int m, int wc,
+                                         const int32_t *rk, int b, int w_lo, int w0, int tw_n,
+                                         int k, int tables, int TW, int lg_tpr, int bx, int nbx,
+                                         const uint64_t *linv, const uint64_t *Bbuf,
+                                         int64_t bstride, uint64_t *tu_lds) {
     uint64_t *sLT = tu_lds;                 // [8][256]   combinations of L^{-1} rows
     uint64_t *sInv = sLT + 8 * 256;         // [64]
     uint64_t *sB = sInv + 64;               // [64][TW]
@@ -282,11 +286,9 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
     const int R1 = rk[b + 1];
     const int r = R1 - R;
     if (r <= 0) return;
-    const bool pivots_here = blockIdx.x == 0;
+    const bool pivots_here = bx == 0;
     if (!pivots_here && R1 >= m) return;
     const int tid = threadIdx.x;
-    const int w0 = w_lo + blockIdx.y * TW;
-    const int tw_n = min(TW, w_hi - w0);
     if (tw_n <= 0) return;
     const int wq = tid % TW, pq = tid / TW, pstep = TU_THREADS / TW;
     if (tid < 64) sInv[tid] = linv[tid];
@@ -307,8 +309,8 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
     const int wpt = (TW + (1 << lg_tpr) - 1) >> lg_tpr;   // words per thread (<= TU_TWMAX)
     const int wb = part * wpt;
     const int wn = max(0, min(wpt, tw_n - wb));           // this thread's words
-    const int per = gridDim.x * rpb;
-    int i = R1 + blockIdx.x * rpb + (tid >> lg_tpr);
+    const int per = nbx * rpb;
+    int i = R1 + bx * rpb + (tid >> lg_tpr);
     bool act = i < m;
     uint64_t l = 0;
     uint64_t x[TU_TWMAX];
@@ -385,6 +387,80 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
         for (int t = pq; t < r; t += pstep) A[(int64_t)(R + t) * stride + w0 + wq] = sU[t * TW + wq];
 }
 
+__global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
+    uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk, int b, int w_lo, int w_hi,
+    int k, int tables, int TW, int lg_tpr, const uint64_t *linv, const uint64_t *Bbuf,
+    int64_t bstride) {
+    extern __shared__ uint64_t tu_lds[];
+    const int w0 = w_lo + blockIdx.y * TW;
+    table_update_tile(A, stride, m, wc, rk, b, w_lo, w0, min(TW, w_hi - w0), k, tables, TW, lg_tpr,
+                      blockIdx.x, gridDim.x, linv, Bbuf, bstride, tu_lds);
+}
+
+// The update after panel wc fused with the search of panel wc + 1.  Blocks
+// [1, ...) update words [wc + 2, w_hi) in tiles of TW as table_update_kernel
+// does; block 0 forms the pivot rows' word wc + 1 (U = L^{-1} B, also kept in
+// info->unext) and searches panel wc + 1, giving each row that word's part of
+// the update, l U, when it first loads the row (panel_search<..., true>); the
+// rows it does not reach get it in the post pass.  The search reads and writes
+// word wc + 1 of rows [rk[b + 1], m) and reads their word wc (final since the
+// post pass of panel wc); the other blocks read word wc and write words
+// >= wc + 2 and the pivot rows, which lie above the search's rows.
+__global__ __launch_bounds__(TU_THREADS) void table_update_search_kernel(
+    uint64_t *A, int64_t stride, int m, int n, int wc, int32_t *rk, int b, int w_lo, int w_hi,
+    int k, int tables, int TW, int lg_tpr, int nxr, const uint64_t *linv, const uint64_t *Bbuf,
+    int64_t bstride, int32_t *P, int32_t *Q, PanelInfo *info) {
+    extern __shared__ uint64_t tu_lds[];
+    const int bid = blockIdx.x;
+    if (bid > 0) {
+        const int j = bid - 1, ty = j / nxr;
+        const int w0 = w_lo + 1 + ty * TW;
+        table_update_tile(A, stride, m, wc, rk, b, w_lo, w0, min(TW, w_hi - w0), k, tables, TW,
+                          lg_tpr, j - ty * nxr, nxr, linv, Bbuf, bstride, tu_lds);
+        return;
+    }
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int R = rk[b], R1 = rk[b + 1], r = R1 - R;
+    uint64_t *sUn = tu_lds;             // [64]      U's rows
+    uint64_t *sTU = sUn + 64;           // [8][256]  combinations of U's rows
+    uint64_t *sBw = sTU + 8 * 256;      // [64]      B's rows (word wc + 1)
+    uint64_t *sTB = sBw + 64;           // [8][256]  combinations of B's rows
+    SearchLds &S = *reinterpret_cast<SearchLds *>(sTB + 8 * 256);
+    if (tid >= LEAF_THREADS && tid < LEAF_THREADS + 2 * LEAF_W) {
+        // bring the first window's words wc and wc + 1 into the caches while
+        // U is formed (the value is only consumed, so the load must land)
+        const int e = tid - LEAF_THREADS, o = R1 + (e >> 1);
+        if (o < m) {
+            const uint64_t pf = A[(int64_t)o * stride + wc + (e & 1)];
+            asm volatile("" ::"v"(pf));
+        }
+    }
+    // U = L^{-1} B on word wc + 1: row t is the combination of B's rows selected
+    // by row t of L^{-1}, one lookup per 8 of them
+    uint64_t lv = 0;
+    if (tid < 64) {
+        lv = tid < r ? linv[tid] : 0ull;
+        sBw[tid] = tid < r ? Bbuf[(int64_t)tid * bstride] : 0ull;
+    }
+    __syncthreads();
+    build_tables_8x8<TU_THREADS, true>(sBw, sTB, tid);
+    if (tid < 64) {
+        const uint64_t u = add_lu(0ull, lv, sTB);
+        sUn[tid] = u;
+        info->unext[tid] = u;
+        if (tid < r) A[(int64_t)(R + tid) * stride + wc + 1] = u;
+    }
+    __syncthreads();
+    build_tables_8x8<TU_THREADS, true>(sUn, sTU, tid);
+    // the search runs on the first LEAF_THREADS threads; the other waves end here
+    // (a barrier waits for the waves that have not ended)
+    if (wave >= LEAF_THREADS / 64) return;
+    const int r2 = panel_search<LEAF_THREADS, true>(A, stride, m, n, wc + 1, R1, P, Q, info, S,
+                                                    nullptr, false, sTU);
+    if (tid == 0) rk[b + 2] = R1 + r2;
+}
+
 hipError_t launch_table_update(uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk,
                                int b, int w_lo, int w_hi, int k, int tables, const uint64_t *linv,
                                const uint64_t *Bbuf, int64_t bstride, int target_blocks,
@@ -412,6 +488,43 @@ hipError_t launch_table_update(uint64_t *A, int64_t stride, int m, int wc, const
     }
     hipLaunchKernelGGL(table_update_kernel, dim3(nx, ny), dim3(TU_THREADS), lds, st, A, stride, m,
                        wc, rk, b, w_lo, w_hi, k, tables, TW, lg_tpr, linv, Bbuf, bstride);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_update_search(uint64_t *A, int64_t stride, int m, int n, int wc, int32_t *rk,
+                                      int b, int w_lo, int w_hi, int k, int tables,
+                                      const uint64_t *linv, const uint64_t *Bbuf, int64_t bstride,
+                                      int32_t *P, int32_t *Q, int32_t *infobuf, int target_blocks,
+                                      hipStream_t st) {
+    if (w_hi <= w_lo) return hipErrorInvalidValue;
+    const int nrest = w_hi - w_lo - 1;
+    int TW = table_update_tile_words(k, tables);
+    if (TW > nrest) TW = std::max(nrest, 1);
+    const int ny = nrest > 0 ? (nrest + TW - 1) / TW : 0;
+    const size_t search_lds = 2 * (64 + 8 * 256) * 8 + sizeof(SearchLds);
+    const size_t lds = std::max(ny > 0 ? table_update_lds_bytes(k, tables, TW) : 0, search_lds);
+    const int occ = std::max(1, (int)(CU_LDS / lds));
+    const int slots = std::max(2, target_blocks * occ);
+    int nxr = 0, lg_tpr = 0;
+    if (ny > 0) {
+        lg_tpr = TW >= 4 ? 2 : (TW >= 2 ? 1 : 0);
+        const int rpb = TU_THREADS >> lg_tpr;
+        nxr = (m + rpb - 1) / rpb;
+        const int fit = std::max(1, (slots - 1) / ny);
+        if (nxr > fit) nxr = fit;
+        if (nxr < 1) nxr = 1;
+    }
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)table_update_search_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, TU_LDS_MAX);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    PanelInfo *info = reinterpret_cast<PanelInfo *>(infobuf);
+    hipLaunchKernelGGL(table_update_search_kernel, dim3(1 + nxr * ny), dim3(TU_THREADS), lds, st, A,
+                       stride, m, n, wc, rk, b, w_lo, w_hi, k, tables, TW, lg_tpr, std::max(nxr, 1),
+                       linv, Bbuf, bstride, P, Q, info);
     return hipGetLastError();
 }
 
