@@ -245,35 +245,46 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
                 // when fl == es).
                 // cc and tt advance together here, so one bound covers both limits
                 const int lim = min(nc, cc + (mrem - tt));
-                while (cc < lim) {
-                    const uint64_t b0 = readlane64(c0, cc) & m0;
-                    if (!b0) break;
+                // all-ones in lanes j > cc (the columns right of the current one)
+                uint32_t gt = lane > cc ? ~0u : 0u;
+                // candidates of column cc, none once cc reaches lim (a lane index
+                // of 64 reads lane 0, whose value is then dropped)
+                uint64_t b0 = readlane64(c0, cc & 63) & m0;
+                if (cc >= lim) b0 = 0;
+                while (b0) {
                     const uint64_t b1 = readlane64(c1, cc) & m1;
                     const int es = tt - tsu;   // < 64: pivots fill the window from its start
                     const int fl = __ffsll((unsigned long long)b0) - 1;
                     const uint64_t E0 = b0 & ~(1ull << fl);
-                    // all-ones in lanes j > cc whose pivot bit is set (arithmetic,
-                    // not a select)
-                    const uint32_t f32 =
-                        0u - ((uint32_t)(c0 >> fl) & ((uint32_t)(cc - lane) >> 31) & 1u);
+                    // all-ones in lanes j > cc whose pivot bit is set (a sign-extended
+                    // one-bit field of the half holding bit fl)
+                    const uint32_t hf = fl < 32 ? (uint32_t)c0 : (uint32_t)(c0 >> 32);
+                    const uint32_t f32 = (uint32_t)__builtin_amdgcn_sbfe((int)hf, fl & 31, 1) & gt;
                     c0 = ((uint64_t)xor_and_s((uint32_t)(c0 >> 32), (uint32_t)(E0 >> 32), f32) << 32) |
                          xor_and_s((uint32_t)c0, (uint32_t)E0, f32);
                     c1 = ((uint64_t)xor_and_s((uint32_t)(c1 >> 32), (uint32_t)(b1 >> 32), f32) << 32) |
                          xor_and_s((uint32_t)c1, (uint32_t)b1, f32);
-                    const uint64_t d = ((c0 >> es) ^ (c0 >> fl)) & 1ull;
-                    const uint64_t de = d << es, df = d << fl;
-                    c0 = ((uint64_t)xor_or((uint32_t)(c0 >> 32), (uint32_t)(de >> 32), (uint32_t)(df >> 32)) << 32) |
-                         xor_or((uint32_t)c0, (uint32_t)de, (uint32_t)df);
-                    // entries es and fl of the original-row record trade places
-                    // (lane writes; when es == fl both write the same value)
-                    const int ogs = __builtin_amdgcn_readlane(og0, es);
-                    const int oge = __builtin_amdgcn_readlane(og0, fl);
-                    og0 = gf2_amdgcn_writelane(oge, es, og0);
-                    og0 = gf2_amdgcn_writelane(ogs, fl, og0);
+                    if (fl != es) {
+                        // entries es and fl trade places, in the window and in the
+                        // original-row record
+                        const uint64_t d = ((c0 >> es) ^ (c0 >> fl)) & 1ull;
+                        const uint64_t de = d << es, df = d << fl;
+                        c0 = ((uint64_t)xor_or((uint32_t)(c0 >> 32), (uint32_t)(de >> 32), (uint32_t)(df >> 32)) << 32) |
+                             xor_or((uint32_t)c0, (uint32_t)de, (uint32_t)df);
+                        const int ogs = __builtin_amdgcn_readlane(og0, es);
+                        const int oge = __builtin_amdgcn_readlane(og0, fl);
+                        og0 = gf2_amdgcn_writelane(oge, es, og0);
+                        og0 = gf2_amdgcn_writelane(ogs, fl, og0);
+                    }
                     fer = gf2_amdgcn_writelane(fl, cc, fer);
                     m0 &= ~(1ull << es);
                     tt++;
                     cc++;
+                    // lane cc drops out (cc & 63: at cc = 64 the loop ends, and
+                    // lane 0 is already clear)
+                    gt = (uint32_t)gf2_amdgcn_writelane(0, cc & 63, (int)gt);
+                    b0 = readlane64(c0, cc & 63) & m0;
+                    if (cc >= lim) b0 = 0;
                 }
                 if (!(cc < nc && tt < mrem)) break;
                 // no first-half entry has a one in column cc
