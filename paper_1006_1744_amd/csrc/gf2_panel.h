@@ -115,6 +115,20 @@ __device__ inline uint64_t apply_tables(uint64_t x, const int32_t *q, int ta, in
     return x;
 }
 
+// All-ones if bit 0 of x is set, else zero (one v_bfe_i32; left to itself the
+// compiler turns the field extract into a compare and a select).
+__device__ inline uint32_t sext_bit0(uint32_t x) {
+    uint32_t r;
+    asm("v_bfe_i32 %0, %1, 0, 1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// v with bit b cleared (wave-uniform, one scalar instruction).
+__device__ inline uint64_t sbitclear64(uint64_t v, int b) {
+    asm("s_bitset0_b64 %0, %1" : "+s"(v) : "s"(b));
+    return v;
+}
+
 // Value v (wave-uniform) written into lane l of a per-lane register.
 __device__ inline uint64_t writelane64(uint64_t old, uint64_t v, int l) {
     return (int)__lane_id() == l ? v : old;
@@ -249,17 +263,15 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
                 uint32_t gt = lane > cc ? ~0u : 0u;
                 // candidates of column cc, none once cc reaches lim (a lane index
                 // of 64 reads lane 0, whose value is then dropped)
-                uint64_t b0 = readlane64(c0, cc & 63) & m0;
-                if (cc >= lim) b0 = 0;
+                uint64_t b0 = readlane64(c0, cc & 63) & m0 & (cc < lim ? ~0ull : 0ull);
                 while (b0) {
                     const uint64_t b1 = readlane64(c1, cc) & m1;
                     const int es = tt - tsu;   // < 64: pivots fill the window from its start
                     const int fl = __ffsll((unsigned long long)b0) - 1;
-                    const uint64_t E0 = b0 & ~(1ull << fl);
-                    // all-ones in lanes j > cc whose pivot bit is set (a sign-extended
-                    // one-bit field of the half holding bit fl)
-                    const uint32_t hf = fl < 32 ? (uint32_t)c0 : (uint32_t)(c0 >> 32);
-                    const uint32_t f32 = (uint32_t)__builtin_amdgcn_sbfe((int)hf, fl & 31, 1) & gt;
+                    const uint64_t E0 = sbitclear64(b0, fl);
+                    // all-ones in lanes j > cc whose pivot bit is set (bit fl brought
+                    // down, then sign-extended)
+                    const uint32_t f32 = sext_bit0((uint32_t)(c0 >> fl)) & gt;
                     c0 = ((uint64_t)xor_and_s((uint32_t)(c0 >> 32), (uint32_t)(E0 >> 32), f32) << 32) |
                          xor_and_s((uint32_t)c0, (uint32_t)E0, f32);
                     c1 = ((uint64_t)xor_and_s((uint32_t)(c1 >> 32), (uint32_t)(b1 >> 32), f32) << 32) |
@@ -277,14 +289,13 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
                         og0 = gf2_amdgcn_writelane(ogs, fl, og0);
                     }
                     fer = gf2_amdgcn_writelane(fl, cc, fer);
-                    m0 &= ~(1ull << es);
+                    m0 = sbitclear64(m0, es);
                     tt++;
                     cc++;
                     // lane cc drops out (cc & 63: at cc = 64 the loop ends, and
                     // lane 0 is already clear)
                     gt = (uint32_t)gf2_amdgcn_writelane(0, cc & 63, (int)gt);
-                    b0 = readlane64(c0, cc & 63) & m0;
-                    if (cc >= lim) b0 = 0;
+                    b0 = readlane64(c0, cc & 63) & m0 & (cc < lim ? ~0ull : 0ull);
                 }
                 if (!(cc < nc && tt < mrem)) break;
                 // no first-half entry has a one in column cc
