@@ -148,6 +148,12 @@ struct SearchLds {
     uint64_t sE[8][256];   // pivots of the last epoch, for rows in [window end, F)
     int s_t, s_c, s_F, s_pa, s_brk, s_far, s_tab_lo, s_tab_hi, s_epochs;
     int sOg[LEAF_W];       // first window: original offset of each entry's row
+    // OR of the rows past the window, taken by a far search that found no row
+    // with a one; it stays exact for every column while no pivot found since has
+    // a one there in it (s_or_ok)
+    unsigned long long s_orv;
+    int s_or_ok;
+    int s_touch;           // the last epoch's pivots may have ones in those rows
 };
 
 // Row `lane` of L^{-1} for a panel with ru pivots, lane t holding pivot word
@@ -191,6 +197,7 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
     uint64_t (*sE)[256] = S.sE;
     int &s_t = S.s_t, &s_c = S.s_c, &s_F = S.s_F, &s_pa = S.s_pa, &s_brk = S.s_brk;
     int &s_far = S.s_far, &s_tab_lo = S.s_tab_lo, &s_tab_hi = S.s_tab_hi, &s_epochs = S.s_epochs;
+    int &s_or_ok = S.s_or_ok;
     int *sOg = S.sOg;
 
     // wave index made visibly uniform, so that the one-wave sections below are
@@ -204,7 +211,7 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
 
     if (tid == 0) {
         s_t = 0; s_c = 0; s_F = 0; s_pa = 0; s_tab_lo = -1; s_tab_hi = -1; s_brk = 0;
-        s_far = NOHIT; s_epochs = 0;
+        s_far = NOHIT; s_epochs = 0; s_or_ok = 0;
     }
     __syncthreads();
 
@@ -213,6 +220,11 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
     while (true) {
         const int t = s_t, c = s_c, F = s_F, pa = s_pa, tl = s_tab_lo, th = s_tab_hi;
         const int epochs = s_epochs;
+        // (block-uniform values, kept in scalar registers)
+        const int or_ok = __builtin_amdgcn_readfirstlane(s_or_ok);
+        const uint64_t orv0 = S.s_orv;
+        const uint64_t orv = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(orv0 >> 32)) << 32) |
+                             (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)orv0);
         __syncthreads();
         if (mrem <= 0 || c >= nc || t >= mrem) break;
         if (epochs > 0) simple = false;
@@ -324,6 +336,20 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
                     cc++;
                     continue;
                 }
+                if (or_ok) {
+                    // zero in every row past the window too, if no pivot since the
+                    // last full far search has touched those rows.  The tables
+                    // take an epoch's pivot columns as consecutive, so the column
+                    // is skipped in place only before the epoch's first pivot;
+                    // otherwise the epoch ends here (no far search) and the next
+                    // one starts with it
+                    const uint64_t piv = __ballot(fer >= 0);
+                    if (!((piv | (1ull << cc)) & orv)) {
+                        if (tt != tsu) break;
+                        cc++;
+                        continue;
+                    }
+                }
                 brk = 1;
                 break;
             }
@@ -333,6 +359,9 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
             if (o1 < mrem) col[(int64_t)o1 * stride] = x1;
             // bookkeeping of the pivots [t, tt), one lane per column
             const uint64_t isp = __ballot(fer >= 0);
+            // do this epoch's pivots touch the rows past the window?
+            const bool touch = !or_ok || (isp & orv) != 0;
+            if (or_ok && touch && lane == 0) s_or_ok = 0;
             if (fer >= 0) {
                 const int pidx = t + __popcll(isp & ((1ull << lane) - 1));
                 P[R + pidx] = R + ts + fer;
@@ -350,17 +379,18 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
                 s_c = cc;
                 s_brk = brk;
                 s_epochs = epochs + 1;
+                S.s_touch = touch;
                 const int nF = max(F, min(ts + LEAF_W, mrem));
                 s_F = nF;
                 if (nF >= mrem) s_pa = tt;   // no row is left past the frontier
             }
         }
         __syncthreads();
-        const int t1 = s_t, c1 = s_c, brk = s_brk;
+        const int t1 = s_t, c1 = s_c, brk = s_brk, touch = S.s_touch;
         __syncthreads();
         // Rows between the window and an older frontier miss this epoch's pivots.
         const int wend = min(ts + LEAF_W, mrem);
-        if (t1 > ts && F > wend) {
+        if (t1 > ts && F > wend && touch) {
             build_tables<NT>(sU, sQ, ts, t1, sE, tid);
             __syncthreads();
             for (int o = wend + tid; o < F; o += NT)
@@ -376,10 +406,11 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
         __syncthreads();
         const bool need2 = F2 < mrem && t1 > pa2 && (tl2 != pa2 || th2 != t1);
         if (need2) build_tables<NT>(sU, sQ, pa2, t1, sT, tid);
-        if (tid == 0) s_far = NOHIT;
+        if (tid == 0) { s_far = NOHIT; S.s_orv = 0; }
         __syncthreads();
         if (need2 && tid == 0) { s_tab_lo = pa2; s_tab_hi = t1; }
         int scan_end = wend;
+        uint64_t acc = 0;   // OR of this thread's scanned rows
         for (int base = wend; base < mrem; base += NT) {
             const int o = base + tid;
             if (o < mrem) {
@@ -389,6 +420,7 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
                     if (t1 > pa2) v = apply_tables(v, sQ, pa2, t1, sT);
                     col[(int64_t)o * stride] = v;
                 }
+                acc |= v;
                 if ((v >> c1) & 1) atomicMin(&s_far, o);
             }
             scan_end = min(base + NT, mrem);
@@ -400,8 +432,10 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
         const int f = s_far;
         const int F3 = max(F2, scan_end);
         if (f == NOHIT) {
-            // column c1 is zero in every remaining row; every row is reduced now
-            if (tid == 0) { s_c = c1 + 1; s_F = F3; s_pa = t1; }
+            // column c1 is zero in every remaining row; every row is reduced now,
+            // and the scan covered every row past the window
+            if (acc) atomicOr(&S.s_orv, (unsigned long long)acc);
+            if (tid == 0) { s_c = c1 + 1; s_F = F3; s_pa = t1; s_or_ok = 1; }
             __syncthreads();
             continue;
         }
@@ -433,6 +467,7 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
             s_F = F3;
             s_pa = F3 >= mrem ? t1 + 1 : pa2;
             s_epochs = 2;   // moved rows no longer follow from one window
+            s_or_ok = 0;    // the scan stopped at the hit
         }
         __syncthreads();
     }
