@@ -84,7 +84,7 @@ void gf2_ctx_destroy(gf2_ctx *ctx);
 /* Human-readable name of a status code (static storage). */
 const char *gf2_status_str(int status);
 
-/* The fixed default schedule (k 8, tables 8, cutoff 512, GF2_SCHUR_FP4), the
+/* The fixed default schedule (k 8, tables 8, cutoff 2048, GF2_SCHUR_FP4), the
  * fallback of any tuned or learned choice. */
 void gf2_default_sched(gf2_sched *out);
 

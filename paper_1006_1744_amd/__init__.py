@@ -200,7 +200,7 @@ def default_sched() -> Sched:
     return s
 
 
-def sched(k=8, tables=8, cutoff=512, schur=SCHUR_FP4) -> Sched:
+def sched(k=8, tables=8, cutoff=2048, schur=SCHUR_FP4) -> Sched:
     return Sched(k, tables, cutoff, schur)
 
 

@@ -47,7 +47,7 @@ SINGLE_DATA_PATH = os.path.join(HERE, "data", "single_timings.npz")
 # autotuner's space that spans all four of its dimensions.
 SINGLE_TABLE = [(k, t, c, sc) for k in (6, 8) for t in (4, 8)
                 for c in (256, 512, 1024, 2048, 4096) for sc in (0, 1, 2)]
-SINGLE_DEFAULT = SINGLE_TABLE.index((8, 8, 512, 2))
+SINGLE_DEFAULT = SINGLE_TABLE.index((8, 8, 2048, 2))
 SINGLE_LOG2_RANGE = (6.0, 16.0)
 
 

@@ -104,7 +104,7 @@ gf2_sched default_sched() {
     gf2_sched s;
     s.k = 8;
     s.tables = 8;
-    s.cutoff = 512;
+    s.cutoff = 2048;
     s.schur = GF2_SCHUR_FP4;
     return s;
 }
