@@ -96,10 +96,6 @@ int trsm_block_max_rows();
 // every row below adds l U, l its compressed panel word; B (the pivot rows as
 // staged by launch_leaf) is read from Bbuf, L^{-1} from `linv` (64 rows).
 // k bits per table, `tables` tables per pass over the rows.
-hipError_t launch_table_update(uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk,
-                               int b, int w_lo, int w_hi, int k, int tables, const uint64_t *linv,
-                               const uint64_t *Bbuf, int64_t bstride, int target_blocks,
-                               hipStream_t st);
 // The same update (w_hi > w_lo = wc + 1) fused with the search of the next panel
 // (word wc + 1, rows [rk[b + 1], m); writes rk[b + 2], P, Q and *info as
 // launch_leaf_search does).  The rows the search does not reach (offsets >= F of

@@ -6,11 +6,12 @@
 //                    block substitution with tables of 16 combinations of 4 rows
 //                    (MakeTable with k = 4, Section 3.1; AddRowsFromTable,
 //                    Appendix A).
-// table_update_kernel Schur update after one panel: every row below the
+// table_update_search_kernel  Schur update after one panel (every row below the
 //                    panel's pivot rows adds L[i] * U on the target columns, with
 //                    L[i] the row's (final, compressed) panel word and U the
 //                    pivot rows; one table per k multipliers, `tables` tables per
-//                    pass over the rows.
+//                    pass over the rows), with the next panel's search in its
+//                    first block.
 // compress_shift_kernel  final "compress L" of Section 5.
 // finalize_kernel    P, Q tails and the rank.
 #include <algorithm>
@@ -330,16 +331,18 @@ __device__ inline void table_update_tile(uint64_t *A, int64_t stride, int m, int
     const int nrows = m - R1;
     const int nchunks = nrows > 0 ? (nrows + per - 1) / per : 1;
     for (int chunk = 0; chunk < nchunks; chunk++) {
-        if (chunk > 0) {
-            i += per;
-            act = i < m;
-            px += (int64_t)per * stride;
-            if (act) {
-                l = A[(int64_t)i * stride + wc];
+        // the next chunk's row (this thread's too) is requested before this
+        // chunk's work, so its load is in flight while this one is updated
+        const int in = i + per;
+        const bool actn = chunk + 1 < nchunks && in < m;
+        uint64_t *pxn = px + (int64_t)per * stride;
+        uint64_t ln = 0;
+        uint64_t xn[TU_TWMAX];
+        if (actn) {
+            ln = A[(int64_t)in * stride + wc];
 #pragma unroll
-                for (int w = 0; w < TU_TWMAX; w++)
-                    if (w < wn) x[w] = px[w];
-            }
+            for (int w = 0; w < TU_TWMAX; w++)
+                if (w < wn) xn[w] = pxn[w];
         }
         uint64_t c = 0;
         for (int pass = 0; pass < npass; pass++) {
@@ -382,24 +385,19 @@ __device__ inline void table_update_tile(uint64_t *A, int64_t stride, int m, int
             for (int w = 0; w < TU_TWMAX; w++)
                 if (w < wn) px[w] = x[w];
         }
+        i = in;
+        act = actn;
+        px = pxn;
+        l = ln;
+#pragma unroll
+        for (int w = 0; w < TU_TWMAX; w++) x[w] = xn[w];
     }
     if (pivots_here && pq < pstep && wq < tw_n)
         for (int t = pq; t < r; t += pstep) A[(int64_t)(R + t) * stride + w0 + wq] = sU[t * TW + wq];
 }
 
-__global__ __launch_bounds__(TU_THREADS) void table_update_kernel(
-    uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk, int b, int w_lo, int w_hi,
-    int k, int tables, int TW, int lg_tpr, const uint64_t *linv, const uint64_t *Bbuf,
-    int64_t bstride) {
-    extern __shared__ uint64_t tu_lds[];
-    const int w0 = w_lo + blockIdx.y * TW;
-    table_update_tile(A, stride, m, wc, rk, b, w_lo, w0, min(TW, w_hi - w0), k, tables, TW, lg_tpr,
-                      blockIdx.x, gridDim.x, linv, Bbuf, bstride, tu_lds);
-}
-
 // The update after panel wc fused with the search of panel wc + 1.  Blocks
-// [1, ...) update words [wc + 2, w_hi) in tiles of TW as table_update_kernel
-// does; block 0 forms the pivot rows' word wc + 1 (U = L^{-1} B, also kept in
+// [1, ...) update words [wc + 2, w_hi) in tiles of TW (table_update_tile); block 0 forms the pivot rows' word wc + 1 (U = L^{-1} B, also kept in
 // info->unext) and searches panel wc + 1, giving each row that word's part of
 // the update, l U, when it first loads the row (panel_search<..., true>); the
 // rows it does not reach get it in the post pass.  The search reads and writes
@@ -459,36 +457,6 @@ __global__ __launch_bounds__(TU_THREADS) void table_update_search_kernel(
     const int r2 = panel_search<LEAF_THREADS, true>(A, stride, m, n, wc + 1, R1, P, Q, info, S,
                                                     nullptr, false, sTU);
     if (tid == 0) rk[b + 2] = R1 + r2;
-}
-
-hipError_t launch_table_update(uint64_t *A, int64_t stride, int m, int wc, const int32_t *rk,
-                               int b, int w_lo, int w_hi, int k, int tables, const uint64_t *linv,
-                               const uint64_t *Bbuf, int64_t bstride, int target_blocks,
-                               hipStream_t st) {
-    if (w_hi <= w_lo) return hipSuccess;
-    int TW = table_update_tile_words(k, tables);
-    if (TW > w_hi - w_lo) TW = w_hi - w_lo;
-    const int ny = (w_hi - w_lo + TW - 1) / TW;
-    const size_t lds = table_update_lds_bytes(k, tables, TW);
-    const int occ = std::max(1, (int)(CU_LDS / lds));
-    // threads per row: 4 from four words up, 2 for two or three, else 1, so that
-    // the rows spread over more blocks (each block builds the same tables)
-    const int lg_tpr = TW >= 4 ? 2 : (TW >= 2 ? 1 : 0);
-    const int rpb = TU_THREADS >> lg_tpr;
-    int nx = (m + rpb - 1) / rpb;
-    const int fit = std::max(1, target_blocks * occ / ny);
-    if (nx > fit) nx = fit;
-    if (nx < 1) nx = 1;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)table_update_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, TU_LDS_MAX);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
-    hipLaunchKernelGGL(table_update_kernel, dim3(nx, ny), dim3(TU_THREADS), lds, st, A, stride, m,
-                       wc, rk, b, w_lo, w_hi, k, tables, TW, lg_tpr, linv, Bbuf, bstride);
-    return hipGetLastError();
 }
 
 hipError_t launch_table_update_search(uint64_t *A, int64_t stride, int m, int n, int wc, int32_t *rk,
