@@ -101,23 +101,30 @@ __device__ inline uint32_t g2_lds_addr(const uint64_t *p) {
     return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint64_t *)p;
 }
 
-// WT x WT MFMA tiles of 32 x 32 per wave, 2 x 2 waves: WT = 4 gives 256 x 256
-// block tiles, WT = 2 gives 128 x 128.  The block walks its tiles' K stages as
-// one sequence (tile i, stage s), so the loads of the next tile's first stages
-// are in flight while the current tile finishes and writes back.
-template <int WT, int NB, bool F4>
-__global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
+// WA x WB MFMA tiles of 32 x 32 per wave, 2 x NWN waves: (WA, WB, NWN) = (4, 2, 4)
+// gives 256 x 256 block tiles with two waves on each SIMD (128 matrix registers
+// each, so one wave's operand unpacking overlaps the other's matrix work),
+// (2, 2, 2) gives 128 x 128 tiles with one wave per SIMD and three blocks per CU.
+// The block walks its tiles' K stages as one sequence (tile i, stage s), so the
+// loads of the next tile's first stages are in flight while the current tile
+// finishes and writes back.
+template <int WA, int WB, int NWN, int NB, bool F4>
+__global__ __launch_bounds__(128 * NWN) void gemm_dma_kernel(uint64_t *C, int64_t sc,
                                                        const uint64_t *A, int64_t sa, int m,
                                                        RowRange rows, int aw, int w_lo, int nw,
                                                        const uint64_t *Bt, int64_t sbt, int nkw,
                                                        RowRange krows, int kmrows,
                                                        const int32_t *rk, int32_t *prof,
                                                        const int32_t *nwd) {
-    constexpr int TM = 64 * WT;             // block tile rows = columns
-    constexpr int CPW = TM / 64;            // 1 KiB chunks per wave per operand and stage
-    constexpr int STAGE = TM * G2_KC;       // words per operand per stage
-    __shared__ __attribute__((aligned(16))) uint64_t sA[NB][STAGE];
-    __shared__ __attribute__((aligned(16))) uint64_t sB[NB][STAGE];
+    constexpr int NW = 2 * NWN;             // waves
+    constexpr int NT = 64 * NW;             // threads
+    constexpr int TM = 64 * WA;             // block tile rows
+    constexpr int TN = 32 * WB * NWN;       // block tile columns
+    constexpr int CPWA = TM / 16 / NW;      // 1 KiB chunks per wave and stage, A
+    constexpr int CPWB = TN / 16 / NW;      // the same for B
+    static_assert(CPWA * 16 * NW == TM && CPWB * 16 * NW == TN, "chunks per wave");
+    __shared__ __attribute__((aligned(16))) uint64_t sA[NB][TM * G2_KC];
+    __shared__ __attribute__((aligned(16))) uint64_t sB[NB][TN * G2_KC];
     if (nwd) nw = min(nw, *nwd);
     int r0, r1;
     eval_range(rk, m, rows, r0, r1);
@@ -137,7 +144,7 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
     const int li = lane & 31, lg = lane >> 5;
     const int tiles_m = (M + TM - 1) / TM;
     const int ncol = nw * 64;
-    const int tiles_n = (ncol + TM - 1) / TM;
+    const int tiles_n = (ncol + TN - 1) / TN;
     const int ntiles = tiles_m * tiles_n;
     const int nfull = nkw / G2_KC;
     const bool ktail = nkw % G2_KC != 0;
@@ -151,15 +158,20 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
     const int lp = (lane & 3) ^ (((lr >> 1) ^ (lr >> 3)) & 3);
     // reader role: word offset of the slot of pair 2 q + lg of this lane's row
     // in row group t (the swizzle is an XOR, so each round has its own offset)
-    int offa[2][WT], offb[2][WT];
+    int offa[2][WA], offb[2][WB];
 #pragma unroll
-    for (int q = 0; q < 2; q++)
+    for (int q = 0; q < 2; q++) {
 #pragma unroll
-        for (int t = 0; t < WT; t++) {
-            const int ra = wm * (TM / 2) + t * 32 + li, rb = wn * (TM / 2) + t * 32 + li;
+        for (int t = 0; t < WA; t++) {
+            const int ra = wm * (32 * WA) + t * 32 + li;
             offa[q][t] = (ra >> 4) * 128 + 2 * g2_slot(ra & 15, 2 * q + lg);
+        }
+#pragma unroll
+        for (int t = 0; t < WB; t++) {
+            const int rb = wn * (32 * WB) + t * 32 + li;
             offb[q][t] = (rb >> 4) * 128 + 2 * g2_slot(rb & 15, 2 * q + lg);
         }
+    }
     // tile i of this block -> first row and first column word (groups of 8 row
     // tiles per column tile)
     auto tile_at = [&](int i, int &row0, int &cw0) {
@@ -168,21 +180,25 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
         const int gsz = min(G2_GROUP, tiles_m - grp * G2_GROUP);
         const int in = tile % (G2_GROUP * tiles_n);
         row0 = r0 + (grp * G2_GROUP + in % gsz) * TM;
-        cw0 = (in / gsz) * (TM / 64);
+        cw0 = (in / gsz) * (TN / 64);
     };
     // DMA cursor: the next step to load is stage n_st of tile n_i, into buffer
     // n_buf; pa / pb hold the tile's per-lane row pointers (rows past the matrix
     // edge load a clamped, valid row, whose outputs are never stored).  Advanced
     // step by step, so no division runs in the stage loop.
     int n_i = 0, n_st = 0, n_buf = 0;
-    const uint64_t *pa[CPW], *pb[CPW];
+    const uint64_t *pa[CPWA], *pb[CPWB];
     auto cursor_tile = [&]() {
         int row0, cw0;
         tile_at(n_i, row0, cw0);
 #pragma unroll
-        for (int c = 0; c < CPW; c++) {
-            const int tr = 16 * (CPW * wave + c) + lr;
+        for (int c = 0; c < CPWA; c++) {
+            const int tr = 16 * (CPWA * wave + c) + lr;
             pa[c] = A + (int64_t)min(row0 + tr, r1 - 1) * sa + aw + 2 * lp;
+        }
+#pragma unroll
+        for (int c = 0; c < CPWB; c++) {
+            const int tr = 16 * (CPWB * wave + c) + lr;
             pb[c] = Bt + (int64_t)min(cw0 * 64 + tr, ncol - 1) * sbt + 2 * lp;
         }
     };
@@ -191,13 +207,12 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
     // ordinary loads) and advance the cursor
     auto issue_next = [&]() {
         if (!(ktail && n_st == nstage - 1)) {
-            const uint32_t la = g2_lds_addr(&sA[n_buf][wave * CPW * 128]);
-            const uint32_t lb = g2_lds_addr(&sB[n_buf][wave * CPW * 128]);
+            const uint32_t la = g2_lds_addr(&sA[n_buf][wave * CPWA * 128]);
+            const uint32_t lb = g2_lds_addr(&sB[n_buf][wave * CPWB * 128]);
 #pragma unroll
-            for (int c = 0; c < CPW; c++) {
-                g2_dma16(pa[c] + n_st * G2_KC, la + 1024 * c);
-                g2_dma16(pb[c] + n_st * G2_KC, lb + 1024 * c);
-            }
+            for (int c = 0; c < CPWA; c++) g2_dma16(pa[c] + n_st * G2_KC, la + 1024 * c);
+#pragma unroll
+            for (int c = 0; c < CPWB; c++) g2_dma16(pb[c] + n_st * G2_KC, lb + 1024 * c);
         }
         n_buf = n_buf == NB - 1 ? 0 : n_buf + 1;
         if (++n_st == nstage) {
@@ -206,23 +221,22 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
         }
     };
     typedef typename std::conditional<F4, v16f, v16i>::type acc_t;
-    acc_t acc[WT][WT];
+    acc_t acc[WA][WB];
     // one round: the MFMAs of the word pairs (xa, xb) a lane read for round q
     auto compute_round = [&](const v4i *xa, const v4i *xb) {
         if constexpr (F4) {
             // one fp4 MFMA (64 K-bits over both lane groups) per 32-bit part
 #pragma unroll
             for (int u = 0; u < 4; u++) {
-                v8i fa[WT], fb[WT];
+                v8i fa[WA], fb[WB];
 #pragma unroll
-                for (int t = 0; t < WT; t++) {
-                    fa[t] = g2_fp4_a((uint32_t)xa[t][u]);
-                    fb[t] = g2_fp4_b((uint32_t)xb[t][u]);
-                }
+                for (int t = 0; t < WA; t++) fa[t] = g2_fp4_a((uint32_t)xa[t][u]);
 #pragma unroll
-                for (int a = 0; a < WT; a++)
+                for (int t = 0; t < WB; t++) fb[t] = g2_fp4_b((uint32_t)xb[t][u]);
 #pragma unroll
-                    for (int b = 0; b < WT; b++)
+                for (int a = 0; a < WA; a++)
+#pragma unroll
+                    for (int b = 0; b < WB; b++)
                         acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
                             fa[a], fb[b], acc[a][b], 4, 4, 0, 127, 0, 127);
             }
@@ -232,18 +246,20 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
             for (int u = 0; u < 4; u++)
 #pragma unroll
                 for (int s = 0; s < 2; s++) {
-                    v4i fa[WT], fb[WT];
+                    v4i fa[WA], fb[WB];
 #pragma unroll
-                    for (int t = 0; t < WT; t++)
+                    for (int v = 0; v < 4; v++) {
 #pragma unroll
-                        for (int v = 0; v < 4; v++) {
+                        for (int t = 0; t < WA; t++)
                             fa[t][v] = (int)(((uint32_t)xa[t][u] >> (4 * s + v)) & 0x01010101u);
+#pragma unroll
+                        for (int t = 0; t < WB; t++)
                             fb[t][v] = (int)(((uint32_t)xb[t][u] >> (4 * s + v)) & 0x01010101u);
-                        }
+                    }
 #pragma unroll
-                    for (int a = 0; a < WT; a++)
+                    for (int a = 0; a < WA; a++)
 #pragma unroll
-                        for (int b = 0; b < WT; b++)
+                        for (int b = 0; b < WB; b++)
                             acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b],
                                                                              acc[a][b], 0, 0, 0);
                 }
@@ -251,10 +267,9 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
     };
     auto read_round = [&](int b, int q, v4i *xa, v4i *xb) {
 #pragma unroll
-        for (int t = 0; t < WT; t++) {
-            xa[t] = *reinterpret_cast<const v4i *>(&sA[b][offa[q][t]]);
-            xb[t] = *reinterpret_cast<const v4i *>(&sB[b][offb[q][t]]);
-        }
+        for (int t = 0; t < WA; t++) xa[t] = *reinterpret_cast<const v4i *>(&sA[b][offa[q][t]]);
+#pragma unroll
+        for (int t = 0; t < WB; t++) xb[t] = *reinterpret_cast<const v4i *>(&sB[b][offb[q][t]]);
     };
     // Make step gn's operands visible to every wave (step gn is stage sn of tile
     // tn).  Before the call each wave has issued all its LDS reads of step gn - 1
@@ -273,14 +288,23 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
             int row0, cw0;
             tile_at(tn, row0, cw0);
             const int kb = nfull * G2_KC;
-            for (int e = tid; e < TM * 4; e += 256) {
+            for (int e = tid; e < TM * 4; e += NT) {
                 const int tr = e >> 2, p = e & 3;
                 const int slot = (tr >> 4) * 128 + 2 * g2_slot(tr & 15, p);
-                const int arow = row0 + tr, brow = cw0 * 64 + tr;
+                const int arow = row0 + tr;
 #pragma unroll
                 for (int h = 0; h < 2; h++) {
                     const int kw = kb + 2 * p + h;
                     sA[b][slot + h] = (arow < r1 && kw < nkw) ? A[(int64_t)arow * sa + aw + kw] : 0ull;
+                }
+            }
+            for (int e = tid; e < TN * 4; e += NT) {
+                const int tr = e >> 2, p = e & 3;
+                const int slot = (tr >> 4) * 128 + 2 * g2_slot(tr & 15, p);
+                const int brow = cw0 * 64 + tr;
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const int kw = kb + 2 * p + h;
                     sB[b][slot + h] = (brow < ncol && kw < nkw) ? Bt[(int64_t)brow * sbt + kw] : 0ull;
                 }
             }
@@ -291,7 +315,8 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
         const bool next_full = gn + 1 < nsteps &&
                                !(ktail && (sn + 1 < nstage ? sn + 2 == nstage : nstage == 1));
         if (next_full) {
-            if constexpr (CPW == 4)
+            static_assert(CPWA + CPWB == 8 || CPWA + CPWB == 4, "DMA loads per wave and step");
+            if constexpr (CPWA + CPWB == 8)
                 asm volatile("s_waitcnt vmcnt(8)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
             else
                 asm volatile("s_waitcnt vmcnt(4)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
@@ -304,7 +329,7 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
     // round-0 reads issued) between step g's two rounds, so the LDS latency and
     // the barrier overlap matrix-core work instead of opening each round.
     static_assert(NB == 3, "three stages in flight");
-    v4i xa0[WT], xb0[WT], xa1[WT], xb1[WT];
+    v4i xa0[WA], xb0[WB], xa1[WA], xb1[WB];
 #pragma unroll
     for (int gi = 0; gi < NB - 1; gi++)
         if (gi < nsteps) issue_next();
@@ -316,9 +341,9 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
     int g = 0;
     for (int i = 0; i < ntb; i++) {
 #pragma unroll
-        for (int a = 0; a < WT; a++)
+        for (int a = 0; a < WA; a++)
 #pragma unroll
-            for (int b = 0; b < WT; b++)
+            for (int b = 0; b < WB; b++)
 #pragma unroll
                 for (int v = 0; v < 16; v++) {
                     // one matrix-register write per element (a float zero vector
@@ -332,9 +357,9 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
             // next stage's first LDS reads overlap round 1 (left alone, the
             // compiler sinks round 0 below the barrier)
 #pragma unroll
-            for (int a = 0; a < WT; a++)
+            for (int a = 0; a < WA; a++)
 #pragma unroll
-                for (int b = 0; b < WT; b++) asm volatile("" : "+a"(acc[a][b]));
+                for (int b = 0; b < WB; b++) asm volatile("" : "+a"(acc[a][b]));
             if (g + 1 < nsteps) {
                 const bool same = st + 1 < nstage;
                 arrive(g + 1, same ? st + 1 : 0, same ? i : i + 1);
@@ -349,14 +374,14 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
             // 32-63: row rlo + 4); each half is written straight into the lane that
             // stores that row.  Lane L ends up with rows 64 h + L of the wave's rows,
             // words q of its columns, every 32-bit half written once.
-            uint32_t ow[WT / 2][WT / 2][2] = {};
+            uint32_t ow[WA / 2][WB / 2][2] = {};
             // the reads below are assembly, so the wait states a matrix-register
             // read needs after the MFMA that wrote it are placed here by hand
             asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7" ::: "memory");
 #pragma unroll
-            for (int a = 0; a < WT; a++)
+            for (int a = 0; a < WA; a++)
 #pragma unroll
-                for (int b = 0; b < WT; b++)
+                for (int b = 0; b < WB; b++)
 #pragma unroll
                     for (int v = 0; v < 16; v++) {
                         // read one matrix register at a time (left to itself the
@@ -373,12 +398,12 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(uint64_t *C, int64_t sc,
             int row0, cw0;
             tile_at(i, row0, cw0);
 #pragma unroll
-            for (int h = 0; h < WT / 2; h++) {
-                const int grow = row0 + wm * (TM / 2) + h * 64 + lane;
+            for (int h = 0; h < WA / 2; h++) {
+                const int grow = row0 + wm * (32 * WA) + h * 64 + lane;
 #pragma unroll
-                for (int q = 0; q < WT / 2; q++) {
+                for (int q = 0; q < WB / 2; q++) {
                     const uint64_t out = (uint64_t)ow[h][q][0] | ((uint64_t)ow[h][q][1] << 32);
-                    const int cw = cw0 + wn * (WT / 2) + q;
+                    const int cw = cw0 + wn * (WB / 2) + q;
                     if (grow < r1 && cw < nw && out) {
                         uint64_t *pc = C + (int64_t)grow * sc + w_lo + cw;
                         *pc ^= out;
@@ -399,17 +424,17 @@ hipError_t launch_gemm_mfma(uint64_t *C, int64_t sc, const uint64_t *A, int64_t 
     // amortize their larger prologue and epilogue (from K = 4096 on the 65536^2
     // recursion); shorter products use 128 x 128 tiles
     if (nw >= 4 && kmax > 2048) {
-        // persistent: one block per CU (256 matrix registers per lane), each
-        // walking its tiles' stages as one pipeline
+        // persistent: one block of eight waves per CU (two per SIMD, 128 matrix
+        // registers each), each block walking its tiles' stages as one pipeline
         int64_t tiles = (int64_t)((m + 255) / 256) * ((nw * 64 + 255) / 256);
         int64_t blocks = tiles < 256 ? tiles : 256;
         if (blocks >= 8) blocks = blocks / 8 * 8;
         if (blocks < 1) blocks = 1;
         if (fp4)
-            hipLaunchKernelGGL((gemm_dma_kernel<4, 3, true>), dim3((unsigned)blocks), dim3(256), 0, st, C,
+            hipLaunchKernelGGL((gemm_dma_kernel<4, 2, 4, 3, true>), dim3((unsigned)blocks), dim3(512), 0, st, C,
                                sc, A, sa, m, rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof, nwd);
         else
-            hipLaunchKernelGGL((gemm_dma_kernel<4, 3, false>), dim3((unsigned)blocks), dim3(256), 0, st, C,
+            hipLaunchKernelGGL((gemm_dma_kernel<4, 2, 4, 3, false>), dim3((unsigned)blocks), dim3(512), 0, st, C,
                                sc, A, sa, m, rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof, nwd);
         return hipGetLastError();
     }
@@ -419,10 +444,10 @@ hipError_t launch_gemm_mfma(uint64_t *C, int64_t sc, const uint64_t *A, int64_t 
     if (blocks >= 8) blocks = blocks / 8 * 8;
     if (blocks < 1) blocks = 1;
     if (fp4)
-        hipLaunchKernelGGL((gemm_dma_kernel<2, 3, true>), dim3((unsigned)blocks), dim3(256), 0, st, C, sc,
+        hipLaunchKernelGGL((gemm_dma_kernel<2, 2, 2, 3, true>), dim3((unsigned)blocks), dim3(256), 0, st, C, sc,
                            A, sa, m, rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof, nwd);
     else
-        hipLaunchKernelGGL((gemm_dma_kernel<2, 3, false>), dim3((unsigned)blocks), dim3(256), 0, st, C, sc,
+        hipLaunchKernelGGL((gemm_dma_kernel<2, 2, 2, 3, false>), dim3((unsigned)blocks), dim3(256), 0, st, C, sc,
                            A, sa, m, rows, aw, w_lo, nw, Bt, sbt, nkw, krows, kmrows, rk, prof, nwd);
     return hipGetLastError();
 }
