@@ -359,8 +359,9 @@ int gf2_features(gf2_ctx *ctx, const gf2_batch_item *items, int64_t count,
  * full-rank input (density 1/2, rank estimate min(m, n)), since a call's
  * density is not known before it runs.  The argmins are kept in the context;
  * a call without a schedule takes the cell nearest to its (log2 m, log2 n), and
- * the default schedule for shapes more than a quarter step outside the grid
- * (outside the training range).  net.params == NULL removes the choice.
+ * the default schedule for shapes more than a quarter step outside the grid or
+ * with log2 m + log2 n above log2_mn_hi (outside the training range: the shapes
+ * the network was trained on).  net.params == NULL removes the choice.
  * Waits on `stream` (the choice is read back).  The workspace holds
  * gf2_ctx_set_learned_workspace_bytes() bytes.
  * gf2_ctx_learned_sched: the schedule a call without one would use for m x n;
@@ -369,7 +370,8 @@ int gf2_features(gf2_ctx *ctx, const gf2_batch_item *items, int64_t count,
 #define GF2_LEARNED_MAX_CELLS 64
 size_t gf2_ctx_set_learned_workspace_bytes(void);
 int gf2_ctx_set_learned(gf2_ctx *ctx, gf2_mlp net, const gf2_sched *table, float log2_lo,
-                        float log2_hi, void *ws, size_t ws_bytes, void *stream);
+                        float log2_hi, float log2_mn_hi, void *ws, size_t ws_bytes,
+                        void *stream);
 int gf2_ctx_learned_sched(gf2_ctx *ctx, int64_t m, int64_t n, gf2_sched *out);
 
 /* Workspace bytes gf2_addmul needs for C (m x n) += A (m x k) * B (k x n). */

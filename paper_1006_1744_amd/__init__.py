@@ -144,7 +144,7 @@ def _load():
     L.gf2_features.restype = i32
     L.gf2_ctx_set_learned_workspace_bytes.argtypes = []
     L.gf2_ctx_set_learned_workspace_bytes.restype = sz
-    L.gf2_ctx_set_learned.argtypes = [vp, MlpNet, vp, fp, fp, vp, sz, vp]
+    L.gf2_ctx_set_learned.argtypes = [vp, MlpNet, vp, fp, fp, fp, vp, sz, vp]
     L.gf2_ctx_set_learned.restype = i32
     L.gf2_ctx_learned_sched.argtypes = [vp, i64, i64, ctypes.POINTER(Sched)]
     L.gf2_ctx_learned_sched.restype = i32
@@ -473,21 +473,22 @@ def features(items: torch.Tensor, count: int, r_hint: torch.Tensor | None = None
 
 
 def set_learned(params: torch.Tensor | None, S: int = 0, table: torch.Tensor | None = None,
-                log2_lo: float = 6.0, log2_hi: float = 16.0, device=None, stream=None):
+                log2_lo: float = 6.0, log2_hi: float = 16.0, log2_mn_hi: float = 31.0, device=None,
+                stream=None):
     """Install (or with params None remove) the learned choice gf2_pls uses when
     it is given no schedule (gf2_ctx_set_learned).  Waits on the stream."""
     dev = torch.cuda.current_device() if device is None else device
     L = get_lib()
     if params is None:
-        _check(L.gf2_ctx_set_learned(ctx(dev), MlpNet(None, 0), None, 0.0, 0.0, None, 0,
+        _check(L.gf2_ctx_set_learned(ctx(dev), MlpNet(None, 0), None, 0.0, 0.0, 0.0, None, 0,
                                      _stream(stream)))
         return
     if table is None or table.dtype != torch.int32 or tuple(table.shape) != (S, 4):
         raise ValueError("table must be an int32 (S, 4) tensor")
     ws = workspace(int(L.gf2_ctx_set_learned_workspace_bytes()), params.device)
     _check(L.gf2_ctx_set_learned(ctx(dev), MlpNet(_f32(params, "params"), S), table.data_ptr(),
-                                 float(log2_lo), float(log2_hi), ws.data_ptr(), ws.numel(),
-                                 _stream(stream)))
+                                 float(log2_lo), float(log2_hi), float(log2_mn_hi), ws.data_ptr(),
+                                 ws.numel(), _stream(stream)))
 
 
 def learned_sched(m: int, n: int, device=None):

@@ -49,6 +49,7 @@ SINGLE_TABLE = [(k, t, c, sc) for k in (6, 8) for t in (4, 8)
                 for c in (256, 512, 1024, 2048, 4096) for sc in (0, 1, 2)]
 SINGLE_DEFAULT = SINGLE_TABLE.index((8, 8, 2048, 2))
 SINGLE_LOG2_RANGE = (6.0, 16.0)
+SINGLE_LOG2_MN_MAX = 31.0   # training shapes hold at most 2^31 entries (sample_single_shapes)
 
 
 def features(m, n, density, r_est) -> np.ndarray:
@@ -161,9 +162,11 @@ class CostModel:
         """As predict, for features already on the device."""
         return costmodel_predict(self.params, self.S, feats_dev.contiguous(), self.table_dev)
 
-    def install(self, log2_lo=SINGLE_LOG2_RANGE[0], log2_hi=SINGLE_LOG2_RANGE[1]):
-        """Make this model the choice of gf2_pls calls without a schedule."""
-        set_learned(self.params, self.S, self.table_dev, log2_lo, log2_hi)
+    def install(self, log2_lo=SINGLE_LOG2_RANGE[0], log2_hi=SINGLE_LOG2_RANGE[1],
+                log2_mn_hi=SINGLE_LOG2_MN_MAX):
+        """Make this model the choice of gf2_pls calls without a schedule, for the
+        shapes it was trained on (the default elsewhere)."""
+        set_learned(self.params, self.S, self.table_dev, log2_lo, log2_hi, log2_mn_hi)
 
     def predict(self, feats) -> torch.Tensor:
         """Per problem, the (k, tables, cutoff, schur) row of the predicted fastest

@@ -45,7 +45,7 @@ struct gf2_ctx {
     // learned schedule choice for calls without a schedule: one schedule per
     // cell of a half-log2 grid of (m, n) over [l_lo, l_hi]^2, row-major by m
     std::vector<gf2_sched> learned;
-    float l_lo = 0.f, l_hi = -1.f;
+    float l_lo = 0.f, l_hi = -1.f, l_mn_hi = -1.f;
     int l_cells = 0;
 };
 
@@ -368,7 +368,7 @@ gf2_sched choose_sched(const gf2_ctx *ctx, int64_t m, int64_t n, bool *learned =
     if (!ctx || ctx->l_cells <= 0 || m <= 0 || n <= 0) return default_sched();
     const double lm = std::log2((double)m), ln = std::log2((double)n);
     if (lm < ctx->l_lo - 0.25 || lm > ctx->l_hi + 0.25 || ln < ctx->l_lo - 0.25 ||
-        ln > ctx->l_hi + 0.25)
+        ln > ctx->l_hi + 0.25 || lm + ln > ctx->l_mn_hi + 0.25)
         return default_sched();
     const int im = std::min(ctx->l_cells - 1, std::max(0, (int)std::lround((lm - ctx->l_lo) * 2.0)));
     const int in = std::min(ctx->l_cells - 1, std::max(0, (int)std::lround((ln - ctx->l_lo) * 2.0)));
@@ -578,7 +578,8 @@ size_t gf2_ctx_set_learned_workspace_bytes(void) {
 }
 
 int gf2_ctx_set_learned(gf2_ctx *ctx, gf2_mlp net, const gf2_sched *table, float log2_lo,
-                        float log2_hi, void *ws, size_t ws_bytes, void *stream) {
+                        float log2_hi, float log2_mn_hi, void *ws, size_t ws_bytes,
+                        void *stream) {
     if (!ctx) return GF2_E_ARG;
     if (!net.params) {   // back to the default for every call without a schedule
         ctx->learned.clear();
@@ -587,6 +588,7 @@ int gf2_ctx_set_learned(gf2_ctx *ctx, gf2_mlp net, const gf2_sched *table, float
     }
     if (net.S < 1 || net.S > GF2_MLP_MAX_S || !table) return GF2_E_ARG;
     if (!(log2_lo >= 0.f && log2_hi >= log2_lo && log2_hi <= 30.f)) return GF2_E_ARG;
+    if (!(log2_mn_hi >= 2.f * log2_lo)) return GF2_E_ARG;
     const int cells = (int)std::lround((log2_hi - log2_lo) * 2.0f) + 1;
     if (cells > GF2_LEARNED_MAX_CELLS) return GF2_E_ARG;
     if (!ws || ws_bytes < gf2_ctx_set_learned_workspace_bytes()) return GF2_E_WORKSPACE;
@@ -616,6 +618,7 @@ int gf2_ctx_set_learned(gf2_ctx *ctx, gf2_mlp net, const gf2_sched *table, float
     ctx->learned = std::move(out);
     ctx->l_lo = log2_lo;
     ctx->l_hi = log2_lo + 0.5f * (cells - 1);
+    ctx->l_mn_hi = log2_mn_hi;
     ctx->l_cells = cells;
     return GF2_OK;
 }

@@ -421,9 +421,9 @@ hipError_t launch_gemm_mfma(uint64_t *C, int64_t sc, const uint64_t *A, int64_t 
     int nkw = (kmax + 63) / 64;
     if (nw <= 0 || nkw <= 0) return hipSuccess;
     // 256 x 256 tiles pay off once the inner dimension is long enough to
-    // amortize their larger prologue and epilogue (from K = 4096 on the 65536^2
+    // amortize their larger prologue and epilogue (from K = 2048 on the 65536^2
     // recursion); shorter products use 128 x 128 tiles
-    if (nw >= 4 && kmax > 2048) {
+    if (nw >= 4 && kmax > 1024) {
         // persistent: one block of eight waves per CU (two per SIMD, 128 matrix
         // registers each), each block walking its tiles' stages as one pipeline
         int64_t tiles = (int64_t)((m + 255) / 256) * ((nw * 64 + 255) / 256);
