@@ -14,7 +14,8 @@
 //  * int8: two 16-byte operands per 32 bits, register v of step s being
 //    (w >> (4 s + v)) & 0x01010101, whose byte t is bit 8 t + 4 s + v of w;
 //  * fp4: one 16-byte operand per 32 bits, register v holding bit 4 n + v of w
-//    in nibble n, as e2m1 values whose A x B products are exactly 1.
+//    in nibble n, as e2m1 values whose A x B products are exactly 1 (four
+//    masks and, per pair of 32-bit parts, one or two 64-bit shifts).
 //
 // 0/1 elements are also what keeps the clock up: the matrix cores' power grows
 // with the number of toggling operand bits, and with 0/1 bytes the chip holds a
@@ -34,29 +35,45 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 // fp4 (e2m1) operands of v_mfma_scale_f32_32x32x64_f8f6f4 from a lane's 32
-// K-bits w: register v holds bit 4 n + v of w in nibble n (n = 0..7), on a
-// nibble bit chosen so that each register needs at most one shift.  A set bit
-// reads on the A side as 0.5, 1, 2, 2 (registers 0-3: e2m1 codes 0001, 0010,
-// 0100, 0100) and on the B side as 2, 1, 0.5, 0.5, so every product of two set
-// bits is exactly 1 and a clear bit reads as 0.  The block scales are 127
-// (2^0) on both sides.
-__device__ inline v8i g2_fp4_a(uint32_t w) {
+// K-bits d: register v holds bit 4 n + v of d in nibble n (n = 0..7), on a
+// nibble bit below the sign bit.  A set bit reads on the A side as 0.5, 1, 2, 1
+// (registers 0-3: e2m1 codes 0001, 0010, 0100, 0010) and on the B side as 2, 1,
+// 0.5, 1, so every product of two set bits is exactly 1 and a clear bit reads
+// as 0.  The block scales are 127 (2^0) on both sides.  The shifted copies come
+// from one 64-bit shift of two consecutive K steps' words (lo, hi): the bits a
+// shift carries across the halves land on nibble bits the masks clear.
+__device__ inline v8i g2_fp4_a(uint32_t d, uint32_t s2) {   // s2: d >> 2
     v8i f;
-    f[0] = (int)(w & 0x11111111u);
-    f[1] = (int)(w & 0x22222222u);
-    f[2] = (int)(w & 0x44444444u);
-    f[3] = (int)((w >> 1) & 0x44444444u);
+    f[0] = (int)(d & 0x11111111u);
+    f[1] = (int)(d & 0x22222222u);
+    f[2] = (int)(d & 0x44444444u);
+    f[3] = (int)(s2 & 0x22222222u);
     f[4] = f[5] = f[6] = f[7] = 0;   // unused by fp4 operands
     return f;
 }
-__device__ inline v8i g2_fp4_b(uint32_t w) {
+__device__ inline v8i g2_fp4_b(uint32_t d, uint32_t s2, uint32_t l2) {   // l2: d << 2
     v8i f;
-    f[0] = (int)((w << 2) & 0x44444444u);
-    f[1] = (int)(w & 0x22222222u);
-    f[2] = (int)((w >> 2) & 0x11111111u);
-    f[3] = (int)((w >> 3) & 0x11111111u);
+    f[0] = (int)(l2 & 0x44444444u);
+    f[1] = (int)(d & 0x22222222u);
+    f[2] = (int)(s2 & 0x11111111u);
+    f[3] = (int)(s2 & 0x22222222u);
     f[4] = f[5] = f[6] = f[7] = 0;
     return f;
+}
+__device__ inline uint64_t g2_pair(uint32_t lo, uint32_t hi) {
+    return ((uint64_t)hi << 32) | lo;
+}
+// one v_lshrrev_b64 / v_lshlrev_b64 (left to itself the compiler splits a 64-bit
+// shift into two 32-bit instructions)
+__device__ inline uint64_t g2_shr2(uint64_t x) {
+    uint64_t y;
+    asm("v_lshrrev_b64 %0, 2, %1" : "=v"(y) : "v"(x));
+    return y;
+}
+__device__ inline uint64_t g2_shl2(uint64_t x) {
+    uint64_t y;
+    asm("v_lshlrev_b64 %0, 2, %1" : "=v"(y) : "v"(x));
+    return y;
 }
 
 // Block tiles of 256 x 256 (4 x 4 MFMA tiles of 32 x 32 per wave, 256
@@ -225,20 +242,38 @@ __global__ __launch_bounds__(128 * NWN) void gemm_dma_kernel(uint64_t *C, int64_
     // one round: the MFMAs of the word pairs (xa, xb) a lane read for round q
     auto compute_round = [&](const v4i *xa, const v4i *xb) {
         if constexpr (F4) {
-            // one fp4 MFMA (64 K-bits over both lane groups) per 32-bit part
+            // one fp4 MFMA (64 K-bits over both lane groups) per 32-bit part; the
+            // shifts run on pairs of parts
 #pragma unroll
-            for (int u = 0; u < 4; u++) {
-                v8i fa[WA], fb[WB];
+            for (int h = 0; h < 2; h++) {
+                uint64_t sa2[WA], sb2[WB], lb2[WB];
 #pragma unroll
-                for (int t = 0; t < WA; t++) fa[t] = g2_fp4_a((uint32_t)xa[t][u]);
+                for (int t = 0; t < WA; t++)
+                    sa2[t] = g2_shr2(g2_pair((uint32_t)xa[t][2 * h], (uint32_t)xa[t][2 * h + 1]));
 #pragma unroll
-                for (int t = 0; t < WB; t++) fb[t] = g2_fp4_b((uint32_t)xb[t][u]);
+                for (int t = 0; t < WB; t++) {
+                    const uint64_t pb = g2_pair((uint32_t)xb[t][2 * h], (uint32_t)xb[t][2 * h + 1]);
+                    sb2[t] = g2_shr2(pb);
+                    lb2[t] = g2_shl2(pb);
+                }
 #pragma unroll
-                for (int a = 0; a < WA; a++)
+                for (int j = 0; j < 2; j++) {
+                    const int u = 2 * h + j;
+                    v8i fa[WA], fb[WB];
 #pragma unroll
-                    for (int b = 0; b < WB; b++)
-                        acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                            fa[a], fb[b], acc[a][b], 4, 4, 0, 127, 0, 127);
+                    for (int t = 0; t < WA; t++)
+                        fa[t] = g2_fp4_a((uint32_t)xa[t][u], (uint32_t)(sa2[t] >> (32 * j)));
+#pragma unroll
+                    for (int t = 0; t < WB; t++)
+                        fb[t] = g2_fp4_b((uint32_t)xb[t][u], (uint32_t)(sb2[t] >> (32 * j)),
+                                         (uint32_t)(lb2[t] >> (32 * j)));
+#pragma unroll
+                    for (int a = 0; a < WA; a++)
+#pragma unroll
+                        for (int b = 0; b < WB; b++)
+                            acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                                fa[a], fb[b], acc[a][b], 4, 4, 0, 127, 0, 127);
+                }
             }
         } else {
             // two int8 MFMAs (32 K-bits each) per 32-bit part
