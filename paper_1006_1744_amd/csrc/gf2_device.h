@@ -16,7 +16,10 @@ extern "C" __device__ int gf2_amdgcn_writelane(int v, int lane, int old)
 
 // Three-input bit operations of gfx950 (v_bitop3_b32; the truth table is
 // indexed by (a << 2) | (b << 1) | c), for the forms the compiler leaves as
-// two instructions.  b is wave-uniform (a scalar register).
+// two instructions.  b is wave-uniform (a scalar register), and must come from a
+// scalar instruction: a vector instruction that reads a scalar register written by
+// another vector instruction (a ballot, a readlane) needs wait states between the
+// two, which the compiler inserts for its own code but not before inline assembly.
 __device__ inline uint32_t xor_and_s(uint32_t a, uint32_t b, uint32_t c) {   // a ^ (b & c)
     uint32_t d;
     asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x78" : "=v"(d) : "v"(a), "s"(b), "v"(c));
