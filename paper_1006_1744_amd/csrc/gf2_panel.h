@@ -154,6 +154,7 @@ struct SearchLds {
     unsigned long long s_orv;
     int s_or_ok;
     int s_touch;           // the last epoch's pivots may have ones in those rows
+    unsigned long long s_dry;   // columns with no candidate in any row of the last window
 };
 
 // Row `lane` of L^{-1} for a panel with ru pivots, lane t holding pivot word
@@ -353,6 +354,9 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
                 brk = 1;
                 break;
             }
+            // columns (lanes) in which no row of the window is a candidate (read
+            // only after an epoch without pivots)
+            const uint64_t dry = tt == tsu ? __ballot(((c0 & m0) | (c1 & m1)) == 0ull) : 0ull;
             x0 = transpose64(c0, lane);
             x1 = transpose64(c1, lane);
             if (o0 < mrem) col[(int64_t)o0 * stride] = x0;
@@ -380,6 +384,7 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
                 s_brk = brk;
                 s_epochs = epochs + 1;
                 S.s_touch = touch;
+                S.s_dry = dry;
                 const int nF = max(F, min(ts + LEAF_W, mrem));
                 s_F = nF;
                 if (nF >= mrem) s_pa = tt;   // no row is left past the frontier
@@ -400,76 +405,94 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
         if (!brk || t1 > ts) continue;
         // Far search: no window row has a one in column c1.  Scan the rows past
         // the window in order, bringing rows >= F up to date, and stop after the
-        // first block-sized chunk holding a hit.
+        // first block-sized chunk holding a hit.  After a hit, the next column
+        // goes straight to another far search while it too has no candidate in
+        // this window (dry): the window rows then have zeros in every far pivot's
+        // column, so no pivot found meanwhile changes them, and reloading them
+        // would find nothing.
         simple = false;
-        const int F2 = s_F, pa2 = s_pa, tl2 = s_tab_lo, th2 = s_tab_hi;
-        __syncthreads();
-        const bool need2 = F2 < mrem && t1 > pa2 && (tl2 != pa2 || th2 != t1);
-        if (need2) build_tables<NT>(sU, sQ, pa2, t1, sT, tid);
-        if (tid == 0) { s_far = NOHIT; S.s_orv = 0; }
-        __syncthreads();
-        if (need2 && tid == 0) { s_tab_lo = pa2; s_tab_hi = t1; }
-        int scan_end = wend;
-        uint64_t acc = 0;   // OR of this thread's scanned rows
-        for (int base = wend; base < mrem; base += NT) {
-            const int o = base + tid;
-            if (o < mrem) {
-                uint64_t v = col[(int64_t)o * stride];
-                if (o >= F2 && (LAZY || t1 > pa2)) {
-                    if constexpr (LAZY) v = add_lu(v, col[(int64_t)o * stride - 1], TU);
-                    if (t1 > pa2) v = apply_tables(v, sQ, pa2, t1, sT);
-                    col[(int64_t)o * stride] = v;
+        const uint64_t dry = S.s_dry;
+        int tf = t1, cf = c1;
+        while (true) {
+            const int F2 = s_F, pa2 = s_pa, tl2 = s_tab_lo, th2 = s_tab_hi;
+            __syncthreads();
+            const bool need2 = F2 < mrem && tf > pa2 && (tl2 != pa2 || th2 != tf);
+            // the row a pivot found here will displace (a window row), requested
+            // before the tables are built
+            const uint64_t tw = tid == 0 ? col[(int64_t)tf * stride] : 0ull;
+            if (need2) build_tables<NT>(sU, sQ, pa2, tf, sT, tid);
+            if (tid == 0) { s_far = NOHIT; S.s_orv = 0; }
+            __syncthreads();
+            if (need2 && tid == 0) { s_tab_lo = pa2; s_tab_hi = tf; }
+            int scan_end = wend;
+            uint64_t acc = 0;   // OR of this thread's scanned rows
+            int o = -1;         // this thread's row of the last chunk scanned, and its value
+            uint64_t v = 0;
+            for (int base = wend; base < mrem; base += NT) {
+                o = base + tid;
+                if (o < mrem) {
+                    v = col[(int64_t)o * stride];
+                    if (o >= F2 && (LAZY || tf > pa2)) {
+                        if constexpr (LAZY) v = add_lu(v, col[(int64_t)o * stride - 1], TU);
+                        if (tf > pa2) v = apply_tables(v, sQ, pa2, tf, sT);
+                        col[(int64_t)o * stride] = v;
+                    }
+                    acc |= v;
+                    if ((v >> cf) & 1) atomicMin(&s_far, o);
                 }
-                acc |= v;
-                if ((v >> c1) & 1) atomicMin(&s_far, o);
+                scan_end = min(base + NT, mrem);
+                __syncthreads();
+                const bool hit = s_far != NOHIT;
+                __syncthreads();
+                if (hit) break;
             }
-            scan_end = min(base + NT, mrem);
-            __syncthreads();
-            const bool hit = s_far != NOHIT;
-            __syncthreads();
-            if (hit) break;
-        }
-        const int f = s_far;
-        const int F3 = max(F2, scan_end);
-        if (f == NOHIT) {
-            // column c1 is zero in every remaining row; every row is reduced now,
-            // and the scan covered every row past the window
-            if (acc) atomicOr(&S.s_orv, (unsigned long long)acc);
-            if (tid == 0) { s_c = c1 + 1; s_F = F3; s_pa = t1; s_or_ok = 1; }
-            __syncthreads();
-            continue;
-        }
-        if (tid == 0) {
-            uint64_t pw = col[(int64_t)f * stride];
-            uint64_t tw = col[(int64_t)t1 * stride];
-            col[(int64_t)t1 * stride] = pw;
-            col[(int64_t)f * stride] = tw;
-            sU[t1] = pw;
-            sQ[t1] = c1;
-            sPrel[t1] = f;
-            P[R + t1] = R + f;
-            Q[R + t1] = 64 * wc + c1;
-        }
-        __syncthreads();
-        {
-            // rows after f up to the new frontier may hold a one in column c1
-            const uint64_t pw = sU[t1];
-            const uint64_t above = c1 == 63 ? 0ull : (~0ull << (c1 + 1));
-            for (int o = f + 1 + tid; o < F3; o += NT) {
-                uint64_t v = col[(int64_t)o * stride];
-                if ((v >> c1) & 1) col[(int64_t)o * stride] = v ^ (pw & above);
+            const int f = s_far;
+            const int F3 = max(F2, scan_end);
+            if (f == NOHIT) {
+                // column cf is zero in every remaining row; every row is reduced
+                // now, and the scan covered every row past the window
+                if (acc) atomicOr(&S.s_orv, (unsigned long long)acc);
+                if (tid == 0) { s_c = cf + 1; s_F = F3; s_pa = tf; s_or_ok = 1; }
+                __syncthreads();
+                break;
             }
+            // the pivot row comes from the thread that scanned it; rows after it
+            // in the last chunk are still in their threads' registers
+            if (o == f) sU[tf] = v;
+            __syncthreads();
+            {
+                // rows after f up to the new frontier may hold a one in column cf
+                const uint64_t pw = sU[tf];
+                const uint64_t above = cf == 63 ? 0ull : (~0ull << (cf + 1));
+                if (o > f && o < mrem && ((v >> cf) & 1)) col[(int64_t)o * stride] = v ^ (pw & above);
+                for (int o2 = max(f + 1, scan_end) + tid; o2 < F3; o2 += NT) {
+                    const uint64_t v2 = col[(int64_t)o2 * stride];
+                    if ((v2 >> cf) & 1) col[(int64_t)o2 * stride] = v2 ^ (pw & above);
+                }
+                if (tid == 0) {
+                    col[(int64_t)tf * stride] = pw;
+                    col[(int64_t)f * stride] = tw;
+                    sQ[tf] = cf;
+                    sPrel[tf] = f;
+                    P[R + tf] = R + f;
+                    Q[R + tf] = 64 * wc + cf;
+                }
+            }
+            __syncthreads();
+            if (tid == 0) {
+                s_t = tf + 1;
+                s_c = cf + 1;
+                s_F = F3;
+                s_pa = F3 >= mrem ? tf + 1 : pa2;
+                s_epochs = 2;   // moved rows no longer follow from one window
+                s_or_ok = 0;    // the scan stopped at the hit
+            }
+            __syncthreads();
+            tf++;
+            cf++;
+            // the rows [tf, wend) are window rows: the chain needs one of them left
+            if (!(cf < nc && tf < mrem && tf < wend && ((dry >> cf) & 1ull))) break;
         }
-        __syncthreads();
-        if (tid == 0) {
-            s_t = t1 + 1;
-            s_c = c1 + 1;
-            s_F = F3;
-            s_pa = F3 >= mrem ? t1 + 1 : pa2;
-            s_epochs = 2;   // moved rows no longer follow from one window
-            s_or_ok = 0;    // the scan stopped at the hit
-        }
-        __syncthreads();
     }
     __syncthreads();
 
