@@ -355,8 +355,8 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
                 break;
             }
             // columns (lanes) in which no row of the window is a candidate (read
-            // only after an epoch without pivots)
-            const uint64_t dry = tt == tsu ? __ballot(((c0 & m0) | (c1 & m1)) == 0ull) : 0ull;
+            // only when a far search follows)
+            const uint64_t dry = brk ? __ballot(((c0 & m0) | (c1 & m1)) == 0ull) : 0ull;
             x0 = transpose64(c0, lane);
             x1 = transpose64(c1, lane);
             if (o0 < mrem) col[(int64_t)o0 * stride] = x0;
@@ -402,12 +402,13 @@ __device__ inline int panel_search(uint64_t *A, int64_t stride, int m, int n, in
                 col[(int64_t)o * stride] = apply_tables(col[(int64_t)o * stride], sQ, ts, t1, sE);
             __syncthreads();
         }
-        if (!brk || t1 > ts) continue;
-        // Far search: no window row has a one in column c1.  Scan the rows past
-        // the window in order, bringing rows >= F up to date, and stop after the
-        // first block-sized chunk holding a hit.  After a hit, the next column
+        if (!brk || t1 >= wend) continue;
+        // Far search: no row left in the window (offsets [t1, wend), reduced by
+        // every pivot and written back) has a one in column c1.  Scan the rows
+        // past the window in order, bringing rows >= F up to date, and stop after
+        // the first block-sized chunk holding a hit.  After a hit, the next column
         // goes straight to another far search while it too has no candidate in
-        // this window (dry): the window rows then have zeros in every far pivot's
+        // those window rows (dry): they then have zeros in every far pivot's
         // column, so no pivot found meanwhile changes them, and reloading them
         // would find nothing.
         simple = false;
