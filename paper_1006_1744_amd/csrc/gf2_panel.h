@@ -159,22 +159,34 @@ struct SearchLds {
 
 // Row `lane` of L^{-1} for a panel with ru pivots, lane t holding pivot word
 // urow = u[t] and pivot column qv = q[t] (identity past ru); one wave.
-// L (ru x ru, pivot order): L[t][s] is bit q[s] of u[t].  Lane j solves L x = e_j
-// column by column (x ^= L[:, s] where x[s] = 1), then the columns of L^{-1} are
-// transposed into rows.  The pivot columns sit one per lane, so the loop reads
-// them by readlane.  Straight-line and unrolled so that the column ballots,
-// which do not depend on x, can be issued ahead of the substitution chain;
-// columns s >= ru - 1 are empty (no lane below ru passes the test), so every
-// step may run.
+// L (ru x ru, pivot order): L[t][s] is bit q[s] of u[t].  Forward substitution
+// by rows: X[t] = e_t + sum of X[s] over s < t with L[t][s] = 1, so at step s
+// row s is final and is added to every later row whose strictly lower part has
+// bit s.  Lane t keeps that part with its bits already in pivot order (gathered
+// through two transposes when some pivot column is not its own index); X[s] has
+// no bits above s, so before step 32 only the low halves change.  Rows past ru
+// stay unit vectors.  Plain code (no inline assembly): the row read back by
+// readlane feeds vector instructions, and the compiler places the wait states
+// that such a read needs.
 __device__ inline uint64_t panel_linv_row(uint64_t urow, int qv, int ru, int lane) {
-    uint64_t xcol = 1ull << lane;
+    uint64_t uq = urow;   // bit s: bit q[s] of this row
+    if (__ballot(lane < ru && qv != lane)) {
+        const uint64_t ct = transpose64(urow, lane);   // lane c: column c over the rows
+        const uint64_t cq = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(ct >> 32), qv) << 32) |
+                            (uint32_t)__shfl((int)(uint32_t)ct, qv);   // lane s: column q[s]
+        uq = transpose64(cq, lane);
+    }
+    const uint64_t l = lane < ru && lane > 0 ? uq & (~0ull >> (64 - lane)) : 0ull;
+    const int llo = (int)(uint32_t)l, lhi = (int)(uint32_t)(l >> 32);
+    uint32_t xlo = lane < 32 ? 1u << lane : 0u;
+    uint32_t xhi = lane >= 32 ? 1u << (lane - 32) : 0u;
 #pragma unroll
     for (int s2 = 0; s2 < 63; s2++) {
-        const int qs = __builtin_amdgcn_readlane(qv, s2);
-        const uint64_t Lcol = __ballot(lane > s2 && lane < ru && ((urow >> qs) & 1ull));
-        xcol ^= ((xcol >> s2) & 1ull) ? Lcol : 0ull;
+        const uint32_t f = (uint32_t)__builtin_amdgcn_sbfe(s2 < 32 ? llo : lhi, s2 & 31, 1);
+        xlo ^= (uint32_t)__builtin_amdgcn_readlane((int)xlo, s2) & f;
+        if (s2 >= 32) xhi ^= (uint32_t)__builtin_amdgcn_readlane((int)xhi, s2) & f;
     }
-    return transpose64(xcol, lane);
+    return ((uint64_t)xhi << 32) | xlo;
 }
 
 // Search of the panel at word column wc over rows [R, m).  Writes P and Q at

@@ -29,8 +29,8 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_search_kernel(
 //    for the table update that follows from the same copies.
 //  * the last block computes the panel's L^{-1} (info->linv and the per-panel
 //    store) from the pivot words and columns the search recorded.
-constexpr int POST_THREADS = 1024;
-constexpr int SWAP_W = 16;
+constexpr int POST_THREADS = 256;
+constexpr int SWAP_W = 8;
 
 template <bool LAZY>
 __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
@@ -46,43 +46,48 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
     __shared__ int32_t sDst[kMaxMoved], sSrc[kMaxMoved];
     __shared__ int32_t sPk[64];
     const int tid = threadIdx.x;
-    const int R = rk[b];
-    const int mrem = m - R;
-    if (mrem <= 0) return;
-    const int r = info->r, F = info->F, pa = info->pa, cmp = info->compress;
+    const bool wave0 = __builtin_amdgcn_readfirstlane(tid >> 6) == 0;
+    const int l64 = tid & 63;
     if (blockIdx.x == gridDim.x - 1) {
-        if (tid < 64) {
-            const uint64_t urow = tid < r ? info->u[tid] : 0ull;
-            const uint64_t lrow = panel_linv_row(urow, info->q[tid], __builtin_amdgcn_readfirstlane(r), tid);
-            info->linv[tid] = lrow;
-            if (linv_store) linv_store[(int64_t)b * 64 + tid] = lrow;
+        // L^{-1} needs the panel record alone (r = 0 when no row was left: unit rows)
+        if (wave0) {
+            const int ru = info->r;
+            const uint64_t lrow = panel_linv_row(l64 < ru ? info->u[l64] : 0ull, info->q[l64], ru, l64);
+            info->linv[l64] = lrow;
+            if (linv_store) linv_store[(int64_t)b * 64 + l64] = lrow;
         }
         return;
     }
-    if ((int)blockIdx.x < nfin) {
-        const bool pend = (F < mrem) && (r > pa);
-        const bool lazy = LAZY && F < mrem;   // rows >= F lack the previous update
-        if (!pend && !cmp && !lazy) return;
+    const bool rows_blk = (int)blockIdx.x < nfin;
+    // Every load that does not depend on the rank goes out with it: the panel
+    // record's words (rows blocks, first wave), its counts, the move list's length
+    uint64_t iu = 0, iun = 0;
+    int iq = 0;
+    if (rows_blk && wave0) {
+        iu = info->u[l64];
+        iq = info->q[l64];
+        if (LAZY) iun = info->unext[l64];
+    }
+    const int R = rk[b];
+    const int r = info->r, F = info->F, pa = info->pa, cmp = info->compress;
+    const int32_t *mv = info->moved;
+    const int nk = mv[0];
+    const int mrem = m - R;
+    if (mrem <= 0) return;
+    if (rows_blk) {
         uint64_t *col = Ab + (int64_t)R * sb + wc;   // the panel word lies in the block
         const int step = nfin * POST_THREADS;
-        // the first row's words are loaded before the tables are built and stay in
-        // flight across the barriers (they wait for LDS traffic only)
-        // (the panel record's words are requested first, so that storing them to
-        // LDS waits for them alone)
-        const bool wave0 = __builtin_amdgcn_readfirstlane(tid >> 6) == 0;
-        const int l64 = tid & 63;
-        uint64_t iu = 0, iun = 0;
-        int iq = 0;
-        if (wave0) {
-            iu = info->u[l64];
-            iq = info->q[l64];
-            if (LAZY) iun = info->unext[l64];
-        }
-        // (addresses clamped to a valid row: the loads are unconditional)
+        // the first row's words are requested as soon as the rank is known, before
+        // the block decides whether it has work, and stay in flight across the
+        // barriers below (they wait for LDS traffic only); addresses are clamped to
+        // a valid row, so the loads are unconditional
         int o = blockIdx.x * POST_THREADS + tid;
         const int64_t oc = (int64_t)min(o, mrem - 1) * sb;
         uint64_t v = col[oc];
         uint64_t lp = LAZY ? col[oc - 1] : 0ull;   // word wc - 1 lies in the block when LAZY
+        const bool pend = (F < mrem) && (r > pa);
+        const bool lazy = LAZY && F < mrem;   // rows >= F lack the previous update
+        if (!pend && !cmp && !lazy) return;
         if (wave0) {
             sU[l64] = iu;
             sQ[l64] = iq;
@@ -115,8 +120,6 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
         }
         return;
     }
-    const int32_t *mv = info->moved;
-    const int nk = mv[0];
     const int w0 = ((int)blockIdx.x - nfin) * SWAP_W;
     if (tid < nk) {
         sDst[tid] = mv[1 + 2 * tid];
@@ -129,25 +132,51 @@ __global__ __launch_bounds__(POST_THREADS) void panel_post_kernel(
     auto wp = [&](int row, int w) -> uint64_t * {
         return (w >= blk_lo && w < blk_hi) ? Ab + (int64_t)row * sb + w : A + (int64_t)row * stride + w;
     };
-    for (int e = tid; e < nk * SWAP_W; e += POST_THREADS) {
+    // every load of this thread first, then the stores (a fixed count per thread,
+    // so that the loads are in flight together)
+    constexpr int NPT = (kMaxMoved * SWAP_W + POST_THREADS - 1) / POST_THREADS;
+    const int ne = nk * SWAP_W;
+    uint64_t sv[NPT];
+#pragma unroll
+    for (int i = 0; i < NPT; i++) {
+        const int e = tid + i * POST_THREADS;
         const int k = e / SWAP_W, w = w0 + e % SWAP_W;
-        if (w < nwords && w != wc) stage[e] = *wp(R + sSrc[k], w);
+        sv[i] = (e < ne && w < nwords && w != wc) ? *wp(R + sSrc[k], w) : 0ull;
+    }
+#pragma unroll
+    for (int i = 0; i < NPT; i++) {
+        const int e = tid + i * POST_THREADS;
+        if (e < ne) stage[e] = sv[i];
     }
     __syncthreads();
-    for (int e = tid; e < nk * SWAP_W; e += POST_THREADS) {
+#pragma unroll
+    for (int i = 0; i < NPT; i++) {
+        const int e = tid + i * POST_THREADS;
         const int k = e / SWAP_W, w = w0 + e % SWAP_W;
-        if (w < nwords && w != wc) *wp(R + sDst[k], w) = stage[e];
+        if (e < ne && w < nwords && w != wc) *wp(R + sDst[k], w) = sv[i];
     }
     // the pivot rows' words on [bw_lo, bw_hi) after the moves: a moved pivot row
     // takes the staged copy, any other is not written by this launch
     const int blo = max(bw_lo, w0), bhi = min(bw_hi, min(w0 + SWAP_W, nwords));
     if (Bbuf != nullptr && bhi > blo) {
         const int bw = bhi - blo;
-        for (int e = tid; e < r * bw; e += POST_THREADS) {
+        constexpr int NPB = (64 * SWAP_W + POST_THREADS - 1) / POST_THREADS;
+        uint64_t bv[NPB];
+#pragma unroll
+        for (int i = 0; i < NPB; i++) {
+            const int e = tid + i * POST_THREADS;
             const int t = e / bw, w = blo + e % bw;
-            const int k = sPk[t];
-            Bbuf[(int64_t)t * bstride + (w - bw_lo)] =
-                k >= 0 ? stage[k * SWAP_W + (w - w0)] : *wp(R + t, w);
+            bv[i] = 0ull;
+            if (e < r * bw) {
+                const int k = sPk[t];
+                bv[i] = k >= 0 ? stage[k * SWAP_W + (w - w0)] : *wp(R + t, w);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NPB; i++) {
+            const int e = tid + i * POST_THREADS;
+            const int t = e / bw, w = blo + e % bw;
+            if (e < r * bw) Bbuf[(int64_t)t * bstride + (w - bw_lo)] = bv[i];
         }
     }
 }
@@ -167,7 +196,7 @@ hipError_t launch_panel_post(uint64_t *A, int64_t stride, uint64_t *Ab, int64_t 
     PanelInfo *info = reinterpret_cast<PanelInfo *>(infobuf);
     int nwords = (n + 63) / 64;
     int nfin = (m + POST_THREADS - 1) / POST_THREADS;
-    if (nfin > 256) nfin = 256;
+    if (nfin > 512) nfin = 512;
     if (nfin < 1) nfin = 1;
     int nswap = (nwords + SWAP_W - 1) / SWAP_W;
     if (lazy)
