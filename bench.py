@@ -76,8 +76,8 @@ TABLE2_E5345_S = {"table2_row1": {"M4RI": 1.94, "PLS": 2.09, "M+P 0.15": 2.33, "
 # counter reads for a 1 GiB plain copy in the same run (x2 and x1).  Valid only
 # for the kernel source and operand type it was taken with (SHA-256 prefix,
 # schur code); otherwise null.
-PMC_TRAFFIC = {"source": "paper_1006_1744_amd/csrc/k_mfma.hip", "sha256_16": "e2dd6817cab32982",
-               "schur": 2, "bytes_per_launch": 77249043,
+PMC_TRAFFIC = {"source": "paper_1006_1744_amd/csrc/k_mfma.hip", "sha256_16": "3062ec207f4955fd",
+               "schur": 2, "bytes_per_launch": 77258952,
                "profile": "profiles/gemm_mfma_traffic_65536.md"}
 
 
