@@ -23,12 +23,30 @@ def e2m1(code: int) -> float:
     return sign * (1.0 + 0.5 * mnt) * 2.0 ** (e - 1)
 
 
+M32 = 0xFFFFFFFF
+
+
 def fp4_a(w: int) -> list[int]:
-    return [w & 0x11111111, w & 0x22222222, w & 0x44444444, (w >> 1) & 0x44444444]
+    return [w & 0x11111111, w & 0x22222222, w & 0x44444444, (w >> 2) & 0x22222222]
 
 
 def fp4_b(w: int) -> list[int]:
-    return [(w << 2) & 0x44444444, w & 0x22222222, (w >> 2) & 0x11111111, (w >> 3) & 0x11111111]
+    return [(w << 2) & 0x44444444, w & 0x22222222, (w >> 2) & 0x11111111, (w >> 2) & 0x22222222]
+
+
+def fp4_pair(lo: int, hi: int, side: str) -> list[list[int]]:
+    """The kernel's form: the shifted copies of two consecutive K steps' words come
+    from one 64-bit shift of (hi:lo) each way, then the same masks."""
+    p = (hi << 32) | lo
+    s2, l2 = p >> 2, (p << 2) & ((1 << 64) - 1)
+    out = []
+    for j, d in enumerate((lo, hi)):
+        sj, lj = (s2 >> (32 * j)) & M32, (l2 >> (32 * j)) & M32
+        if side == "a":
+            out.append([d & 0x11111111, d & 0x22222222, d & 0x44444444, sj & 0x22222222])
+        else:
+            out.append([lj & 0x44444444, d & 0x22222222, sj & 0x11111111, sj & 0x22222222])
+    return out
 
 
 def i8_regs(w: int) -> list[int]:
@@ -63,6 +81,17 @@ def test_fp4_operands_map_each_bit_once():
         assert len(pa) == 1 and pa == pb
         v, n = pa[0]
         assert e2m1((fp4_a(1 << k)[v] >> (4 * n)) & 15) * e2m1((fp4_b(1 << k)[v] >> (4 * n)) & 15) == 1.0
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_fp4_pair_shifts_match_per_word(seed):
+    # the bits a 64-bit shift carries across the two words land where the masks clear
+    rng = random.Random(50 + seed)
+    words = [0, M32, 1, 3, 1 << 30, 1 << 31, 0xC0000003] + [rng.getrandbits(32) for _ in range(200)]
+    for lo in words:
+        for hi in rng.sample(words, 20):
+            assert fp4_pair(lo, hi, "a") == [fp4_a(lo), fp4_a(hi)]
+            assert fp4_pair(lo, hi, "b") == [fp4_b(lo), fp4_b(hi)]
 
 
 @pytest.mark.parametrize("seed", range(2))
