@@ -255,8 +255,8 @@ hipError_t launch_trsm_block(uint64_t *A, int64_t stride, const uint64_t *Lm, in
 // one round.
 constexpr int TU_THREADS = 1024;   // 16 waves hide the table build's latency
 constexpr int TU_TWMAX = 8;
-constexpr int TU_TABLE_LDS = 120 * 1024;   // budget for the B tables of one pass
-constexpr int TU_LDS_MAX = 150 * 1024;
+constexpr int TU_TABLE_LDS = 128 * 1024;   // budget for the B tables of one pass
+constexpr int TU_LDS_MAX = 158 * 1024;
 constexpr int CU_LDS = 160 * 1024;
 
 int table_update_tile_words(int k, int tables) {
