@@ -7,7 +7,10 @@ of the arithmetic, no GPU):
   one, so the parity of the sum is the GF(2) dot product;
 * the butterfly stage of the 64 x 64 bit transpose, in the form where each lane
   sends its value already shifted toward the partner and keeps its own half with
-  one bit select: six stages give the transpose.
+  one bit select: six stages give the transpose;
+* the rows of a panel's L^-1 as the post pass forms them: the strictly lower
+  part of L gathered into pivot order, then forward substitution by rows with
+  only the low 32-bit halves changing before step 32.
 """
 import random
 
@@ -129,3 +132,42 @@ def test_transpose_stages(seed):
     want = [sum(((rows[i] >> j) & 1) << i for i in range(64)) for j in range(64)]
     assert got == want
     assert transpose_stages(got) == rows
+
+
+def linv_rows_model(u: list[int], q: list[int], ru: int) -> list[int]:
+    """Lane t's result of the post pass's L^-1 routine: u[t] the pivot word of
+    row t (0 past ru), q[t] its pivot column (t itself past ru)."""
+    uq = [sum(((u[t] >> q[s]) & 1) << s for s in range(64)) for t in range(64)]
+    low = [uq[t] & ((1 << t) - 1) if 0 < t < ru else 0 for t in range(64)]
+    xlo = [(1 << t) if t < 32 else 0 for t in range(64)]
+    xhi = [(1 << (t - 32)) if t >= 32 else 0 for t in range(64)]
+    for s in range(63):
+        f = [M32 if (low[t] >> s) & 1 else 0 for t in range(64)]   # bit s of the lower part
+        rlo = xlo[s]                                                 # row s, final
+        xlo = [xlo[t] ^ (rlo & f[t]) for t in range(64)]
+        if s >= 32:
+            rhi = xhi[s]
+            xhi = [xhi[t] ^ (rhi & f[t]) for t in range(64)]
+    return [(xhi[t] << 32) | xlo[t] for t in range(64)]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_linv_rows_model_inverts_l(seed):
+    rng = random.Random(200 + seed)
+    ru = [1, 2, 31, 32, 33, 64][seed]
+    # pivot columns: identity for even seeds, a scattered choice for odd ones
+    cols = list(range(64))
+    if seed % 2:
+        rng.shuffle(cols)
+    q = [cols[t] if t < ru else t for t in range(64)]
+    u = [rng.getrandbits(64) if t < ru else 0 for t in range(64)]
+    X = linv_rows_model(u, q, ru)
+    # L[t][s] = bit q[s] of u[t] for s < t < ru, unit diagonal, identity past ru
+    L = [sum((((u[t] >> q[s]) & 1) << s) for s in range(t)) | (1 << t) if t < ru else 1 << t
+         for t in range(64)]
+    for t in range(64):
+        row = 0   # row t of L X over GF(2)
+        for s in range(64):
+            if (L[t] >> s) & 1:
+                row ^= X[s]
+        assert row == 1 << t
